@@ -1,0 +1,184 @@
+/*
+ * corr.h -- C ABI of libcorr, an FX correlator for AMD MI355X (gfx950).
+ *
+ * The operations follow Wayth, Greenhill & Briggs (2009), "A GPU based
+ * real-time software correlation system for the Murchison Widefield Array
+ * prototype" (arXiv:0906.1887):
+ *   - configure N_I inputs and N_C channels (Sec. 4, opening);
+ *   - channelise each input's real sample blocks with an FFT, 2 N_C samples to
+ *     N_C channels with the redundant half dropped (Sec. 2, Sec. 4 "second step");
+ *   - cross-multiply every spectrum with the conjugate of every other and
+ *     accumulate, all N_I(N_I+1)/2 products incl. autos (Sec. 2, Sec. 4
+ *     "third step", Fig. 2);
+ *   - read the accumulators with their update count and reset them (Fig. 1).
+ *
+ * Conventions
+ *   Visibility   V_ij[c] = sum_t x_i[c,t] * conj(x_j[c,t]).
+ *   Output       [n_channels][P][2] (re, im), P = N_I(N_I+1)/2, packed lower
+ *                triangle, row-major: b(i,j) = i(i+1)/2 + j for 0 <= j <= i.
+ *                Element type: int32 for CORR_X_I8, float32 for the other
+ *                engines, float64 for the long-run accumulator.  Im of every
+ *                auto-correlation is written as exactly zero.
+ *   Samples      complex, [n_channels][n_inputs][row_stride] with re, im
+ *                interleaved; CORR_CI8 = int8 re, int8 im (2 B per sample),
+ *                CORR_CF32 = float re, float im (8 B per sample).
+ *   Memory       The caller owns every device buffer, including the workspace
+ *                (size from corr_workspace_bytes); libcorr never allocates
+ *                device memory.  The library owns only the host-side plan.
+ *                All device work is queued on the stream given at creation;
+ *                inputs must stay valid until the stream passes the call.
+ *   Errors       Every call returns a corr_status; out-parameters are written
+ *                only on CORR_OK; no C++ exception crosses this interface.
+ *                A HIP error (launch failure now, or a device fault found at
+ *                the next synchronising call) returns CORR_E_HIP and puts the
+ *                plan in an error state: every later call except
+ *                corr_destroy returns CORR_E_STATE.
+ *   Threading    A plan is used by one host thread at a time.  Different plans
+ *                may be used concurrently from different threads and streams.
+ */
+#ifndef CORR_H
+#define CORR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct corr_plan corr_plan;
+
+typedef enum {
+    CORR_OK = 0,
+    CORR_E_INVAL = -1,        /* bad argument or configuration            */
+    CORR_E_WORKSPACE = -2,    /* workspace missing, too small, misaligned */
+    CORR_E_HIP = -3,          /* HIP runtime error (plan now in error)    */
+    CORR_E_STATE = -4,        /* plan in error state, or wrong call order */
+    CORR_E_OVERFLOW = -5,     /* accumulation would exceed the int32/FP32 bound */
+    CORR_E_SEQ = -6,          /* sample-block sequence gap or duplicate   */
+    CORR_E_BUSY = -7,         /* ring buffer full / result not ready      */
+    CORR_E_UNSUPPORTED = -8   /* valid request this build does not handle */
+} corr_status;
+
+typedef enum {
+    CORR_CF32 = 0,            /* complex float32 pairs                   */
+    CORR_CI8 = 1              /* complex int8 pairs                       */
+} corr_sample_t;
+
+typedef enum {
+    CORR_X_FP32 = 0,          /* plain FP32 vector FMA, FP32 accumulation  */
+    CORR_X_I8 = 1,            /* int8 MFMA, int32 accumulation (CI8 only)  */
+    CORR_X_F16 = 2,           /* FP16 MFMA, FP32 accumulation (CF32 input) */
+    CORR_X_F8 = 3             /* OCP FP8 E4M3 MFMA with a power-of-two
+                                 per-channel scale, FP32 accumulation     */
+} corr_engine_t;
+
+typedef struct {
+    int32_t n_inputs;         /* N_I >= 1                                   */
+    int32_t n_channels;       /* N_C >= 1                                   */
+    int32_t fft_size;         /* 0: X-engine only.  Else the real FFT length,
+                                 which must equal 2*n_channels (F-stage on;
+                                 this build implements 256)                  */
+    int32_t sample_type;      /* corr_sample_t of corr_correlate's input     */
+    int32_t engine;           /* corr_engine_t                               */
+    int32_t max_abs;          /* > 0: samples are integers with |re|,|im| <=
+                                 max_abs (sets the overflow and exactness
+                                 bounds; F-stage output is clipped to it).
+                                 0: float samples (FP32/F16/F8 engines)      */
+    float requant_scale;      /* F-stage: q = clip(rne(s * X_k), +-max_abs)  */
+    int32_t fp64_longrun;     /* nonzero: keep an FP64 long-run accumulator  */
+    int64_t ring_samples;     /* F-stage: ring capacity in time samples per
+                                 channel (one sample per FFT block).
+                                 F16/F8: conversion chunk in samples.        */
+} corr_config;
+
+/* Bytes of device workspace a plan needs for `cfg`.  Host only. */
+corr_status corr_workspace_bytes(const corr_config *cfg, size_t *bytes);
+
+/* Validate `cfg`, carve the caller's workspace (device pointer, >= the size
+ * from corr_workspace_bytes, 256-byte aligned) and queue its initialisation
+ * on `hip_stream` (a hipStream_t; NULL = default stream).  The plan keeps
+ * pointers into the workspace, which must outlive it.  No kernel runs on
+ * data yet.  On success *out holds a new plan (owned by the library, freed
+ * by corr_destroy). */
+corr_status corr_create(const corr_config *cfg, void *d_workspace, size_t ws_bytes,
+                        void *hip_stream, corr_plan **out);
+
+/* Free the host plan.  Does not synchronise or touch device memory.  Safe on
+ * NULL and on a plan in error state. */
+corr_status corr_destroy(corr_plan *plan);
+
+/* F-stage (Sec. 4, steps 1 and 2; the unpack transpose is fused into it).
+ * d_volt: device int8 real voltages, [n_blocks*fft_size][n_inputs], time-major
+ * with the input index fastest (the aggregated order of Sec. 3).  Each block
+ * of fft_size samples of each input is transformed by a real DFT (forward
+ * sign, unnormalised, no window); channels k = 0..fft_size/2-1 are kept (DC
+ * kept, Nyquist dropped), scaled by requant_scale, rounded half to even,
+ * clipped to +-max_abs and appended as one CI8 time sample per block to the
+ * ring [n_channels][n_inputs][.] in the workspace.
+ * first_seq: sequence number of the first block; it must equal the number
+ * that follows the previous call's last block (any value on the first call
+ * or after corr_seq_reset), else CORR_E_SEQ and nothing is done.
+ * CORR_E_BUSY if the ring lacks room for n_blocks more samples (correlate
+ * first).  d_spectra_dbg: optional device float32 [n_channels][n_inputs]
+ * [n_blocks][2] that receives the spectra before requantisation (NULL in
+ * production; parity tests use it).  Asynchronous. */
+corr_status corr_channelise(corr_plan *plan, const int8_t *d_volt, int64_t n_blocks,
+                            uint64_t first_seq, float *d_spectra_dbg);
+
+/* Accept any first_seq on the next corr_channelise call. */
+corr_status corr_seq_reset(corr_plan *plan);
+
+/* X-engine (Sec. 4 "third step"): for every channel and every pair j <= i,
+ * add sum over the n_samples time samples of x_i conj(x_j) to the plan's
+ * integration accumulator.
+ * d_samples: device samples of cfg.sample_type, [n_channels][n_inputs]
+ * [row_stride] (row_stride in samples; 0 means n_samples), of which the first
+ * n_samples of each row are used.  d_samples == NULL correlates the samples
+ * the F-stage has put in the ring (n_samples and row_stride are then
+ * ignored) and empties the ring.
+ * CORR_E_OVERFLOW (before any launch) if, for integer samples, the samples
+ * accumulated since the last reset would exceed 2*max_abs^2*n <= 2^31-1 with
+ * the int32 engine, or 2^24 with the FP32 engine on integer data (exact FP32
+ * sums).  Asynchronous. */
+corr_status corr_correlate(corr_plan *plan, const void *d_samples, int64_t n_samples,
+                           int64_t row_stride);
+
+/* corr_dump `what` flags. */
+#define CORR_DUMP_INTEG    1  /* copy the integration accumulator to dst      */
+#define CORR_DUMP_LONGRUN  2  /* copy the FP64 long-run accumulator to dst    */
+#define CORR_DUMP_FOLD     4  /* first add the integration into the long-run  */
+#define CORR_DUMP_NO_RESET 8  /* keep the integration accumulator             */
+
+/* Read the accumulators (Fig. 1): optionally fold the integration accumulator
+ * into the FP64 long-run sum (L += V, exact for integer V while |L| < 2^53),
+ * copy the integration (INTEG) or long-run (LONGRUN, exclusive with INTEG)
+ * triangle to dst ([n_channels][P][2] of the accumulator's type; host memory
+ * if dst_is_device == 0, else device), then reset the integration
+ * accumulator and its sample count unless NO_RESET.  Raw sums are returned;
+ * dividing by *n_samples_out is the caller's choice.  Synchronises the
+ * plan's stream, so device faults surface here as CORR_E_HIP.
+ * *n_samples_out: time samples accumulated in the integration (before reset).
+ * *exact_out: 1 if every sum is provably exact (integer samples within the
+ * bounds above), else 0.  Either out pointer may be NULL. */
+corr_status corr_dump(corr_plan *plan, int32_t what, void *dst, int32_t dst_is_device,
+                      int64_t *n_samples_out, int32_t *exact_out);
+
+/* Copy the F-stage samples waiting in the ring (not yet correlated) to dst
+ * as dense CI8 [n_channels][n_inputs][n][2], n = *n_samples_out, host memory
+ * if dst_is_device == 0, else device; dst must hold n_channels * n_inputs *
+ * ring_samples * 2 bytes.  For inspection and parity tests of the F-stage
+ * output.  Synchronises the plan's stream. */
+corr_status corr_ring_read(corr_plan *plan, void *dst, int32_t dst_is_device, int64_t *n_samples_out);
+
+/* Bytes of one integration dump (what = CORR_DUMP_INTEG) or long-run dump. */
+corr_status corr_dump_bytes(const corr_plan *plan, int32_t what, size_t *bytes);
+
+/* Static description of a status code. */
+const char *corr_status_str(corr_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CORR_H */

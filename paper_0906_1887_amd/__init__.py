@@ -1,0 +1,127 @@
+"""FX correlator for AMD MI355X (gfx950): Python front of libcorr.
+
+``_lib`` mirrors the C ABI of ``include/corr.h`` name for name.
+``Correlator`` wraps one plan, using torch only for device memory (the
+workspace, output buffers) and the current HIP stream; all correlator work
+runs in libcorr's kernels.
+"""
+from __future__ import annotations
+
+from . import _lib
+from ._lib import (CORR_CF32, CORR_CI8, CORR_DUMP_FOLD, CORR_DUMP_INTEG, CORR_DUMP_LONGRUN,
+                   CORR_DUMP_NO_RESET, CORR_X_F8, CORR_X_F16, CORR_X_FP32, CORR_X_I8, CorrError,
+                   corr_channelise, corr_config, corr_correlate, corr_create, corr_destroy, corr_dump,
+                   corr_dump_bytes, corr_ring_read, corr_seq_reset, corr_status_str, corr_workspace_bytes)
+
+__all__ = [
+    "Correlator", "CorrError", "corr_config", "corr_workspace_bytes", "corr_create", "corr_destroy",
+    "corr_channelise", "corr_seq_reset", "corr_correlate", "corr_dump", "corr_ring_read", "corr_dump_bytes",
+    "corr_status_str", "ENGINES", "SAMPLE_TYPES",
+]
+
+ENGINES = {"fp32": CORR_X_FP32, "i8": CORR_X_I8, "f16": CORR_X_F16, "f8": CORR_X_F8}
+SAMPLE_TYPES = {"cf32": CORR_CF32, "ci8": CORR_CI8}
+
+
+def make_config(n_inputs: int, n_channels: int, engine: str = "i8", sample_type: str = "ci8",
+                fft_size: int = 0, max_abs: int = 7, requant_scale: float = 0.0,
+                ring_samples: int = 0, fp64_longrun: bool = False) -> corr_config:
+    c = corr_config()
+    c.n_inputs = n_inputs
+    c.n_channels = n_channels
+    c.fft_size = fft_size
+    c.sample_type = SAMPLE_TYPES[sample_type]
+    c.engine = ENGINES[engine]
+    c.max_abs = max_abs
+    c.requant_scale = requant_scale
+    c.fp64_longrun = int(bool(fp64_longrun))
+    c.ring_samples = ring_samples
+    return c
+
+
+class Correlator:
+    """One correlator plan on one device.
+
+    Output of ``dump()``: a tensor [n_channels][P][2] (P = n_inputs(n_inputs+1)/2,
+    packed lower triangle b(i,j) = i(i+1)/2 + j), int32 for the int8 engine,
+    float32 otherwise, float64 for the long-run accumulator.
+    """
+
+    def __init__(self, n_inputs: int, n_channels: int, engine: str = "i8", sample_type: str = "ci8",
+                 fft_size: int = 0, max_abs: int = 7, requant_scale: float = 0.0, ring_samples: int = 0,
+                 fp64_longrun: bool = False, device: str = "cuda:0"):
+        import torch
+
+        self._torch = torch
+        self.device = torch.device(device)
+        self.n_inputs = n_inputs
+        self.n_channels = n_channels
+        self.engine = engine
+        self.cfg = make_config(n_inputs, n_channels, engine, sample_type, fft_size, max_abs,
+                               requant_scale, ring_samples, fp64_longrun)
+        self.ws_bytes = corr_workspace_bytes(self.cfg)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.plan = corr_create(self.cfg, self.workspace.data_ptr(), self.ws_bytes, self.stream.cuda_stream)
+        self.n_products = n_inputs * (n_inputs + 1) // 2
+
+    # -- plan calls ---------------------------------------------------------
+    def channelise(self, volt, first_seq: int, spectra_dbg=None) -> None:
+        t = self._torch
+        assert volt.dtype == t.int8 and volt.is_contiguous() and volt.device == self.device
+        n_blocks = volt.shape[0] // self.cfg.fft_size
+        dbg = 0
+        if spectra_dbg is not None:
+            assert spectra_dbg.dtype == t.float32 and spectra_dbg.is_contiguous()
+            assert spectra_dbg.numel() >= self.n_channels * self.n_inputs * n_blocks * 2
+            dbg = spectra_dbg.data_ptr()
+        corr_channelise(self.plan, volt.data_ptr(), n_blocks, first_seq, dbg)
+
+    def correlate(self, samples=None, n_samples: int | None = None, row_stride: int = 0) -> None:
+        if samples is None:
+            corr_correlate(self.plan, 0, 0, 0)
+            return
+        assert samples.device == self.device and samples.is_contiguous()
+        if n_samples is None:
+            n_samples = samples.shape[2]
+        corr_correlate(self.plan, samples.data_ptr(), n_samples, row_stride)
+
+    def correlate_ptr(self, d_samples: int, n_samples: int, row_stride: int = 0) -> None:
+        """Raw form: device pointer to [n_channels][n_inputs][row_stride] samples."""
+        corr_correlate(self.plan, d_samples, n_samples, row_stride)
+
+    def dump(self, what: int = CORR_DUMP_INTEG, out=None, device_out: bool = True):
+        """Returns (tensor, n_samples, exact)."""
+        t = self._torch
+        if what & CORR_DUMP_LONGRUN:
+            dtype = t.float64
+        else:
+            dtype = t.int32 if self.engine == "i8" else t.float32
+        if out is None and (what & (CORR_DUMP_INTEG | CORR_DUMP_LONGRUN)):
+            dev = self.device if device_out else t.device("cpu")
+            out = t.empty((self.n_channels, self.n_products, 2), dtype=dtype, device=dev)
+        ptr = out.data_ptr() if out is not None else 0
+        is_dev = out is not None and out.device.type == "cuda"
+        n, exact = corr_dump(self.plan, what, ptr, is_dev)
+        return out, n, exact
+
+    def ring_read(self):
+        t = self._torch
+        buf = t.empty((self.n_channels, self.n_inputs, max(1, self.cfg.ring_samples), 2), dtype=t.int8)
+        n = corr_ring_read(self.plan, buf.data_ptr(), False)
+        flat = buf.reshape(-1)[: self.n_channels * self.n_inputs * n * 2]
+        return flat.reshape(self.n_channels, self.n_inputs, n, 2)
+
+    def seq_reset(self) -> None:
+        corr_seq_reset(self.plan)
+
+    def close(self) -> None:
+        if getattr(self, "plan", 0):
+            corr_destroy(self.plan)
+            self.plan = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,151 @@
+"""ctypes binding of libcorr's C ABI (include/corr.h), same names, argument
+marshalling only.  Every step of the correlator runs in the HIP library;
+this module raises if the library is not built."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcorr.so")
+
+CORR_OK = 0
+CORR_E_INVAL = -1
+CORR_E_WORKSPACE = -2
+CORR_E_HIP = -3
+CORR_E_STATE = -4
+CORR_E_OVERFLOW = -5
+CORR_E_SEQ = -6
+CORR_E_BUSY = -7
+CORR_E_UNSUPPORTED = -8
+
+CORR_CF32 = 0
+CORR_CI8 = 1
+
+CORR_X_FP32 = 0
+CORR_X_I8 = 1
+CORR_X_F16 = 2
+CORR_X_F8 = 3
+
+CORR_DUMP_INTEG = 1
+CORR_DUMP_LONGRUN = 2
+CORR_DUMP_FOLD = 4
+CORR_DUMP_NO_RESET = 8
+
+EXPORTED = [
+    "corr_workspace_bytes", "corr_create", "corr_destroy", "corr_channelise", "corr_seq_reset",
+    "corr_correlate", "corr_dump", "corr_ring_read", "corr_dump_bytes", "corr_status_str",
+]
+
+
+class corr_config(ctypes.Structure):
+    _fields_ = [
+        ("n_inputs", ctypes.c_int32),
+        ("n_channels", ctypes.c_int32),
+        ("fft_size", ctypes.c_int32),
+        ("sample_type", ctypes.c_int32),
+        ("engine", ctypes.c_int32),
+        ("max_abs", ctypes.c_int32),
+        ("requant_scale", ctypes.c_float),
+        ("fp64_longrun", ctypes.c_int32),
+        ("ring_samples", ctypes.c_int64),
+    ]
+
+
+class CorrError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {corr_status_str(status)} ({status})")
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                               "(there is no fallback implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        I32, I64 = ctypes.c_int32, ctypes.c_int64
+        cfgp = ctypes.POINTER(corr_config)
+        L.corr_workspace_bytes.argtypes = [cfgp, ctypes.POINTER(ctypes.c_size_t)]
+        L.corr_create.argtypes = [cfgp, P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+        L.corr_destroy.argtypes = [P]
+        L.corr_channelise.argtypes = [P, P, I64, ctypes.c_uint64, P]
+        L.corr_seq_reset.argtypes = [P]
+        L.corr_correlate.argtypes = [P, P, I64, I64]
+        L.corr_dump.argtypes = [P, I32, P, I32, ctypes.POINTER(I64), ctypes.POINTER(I32)]
+        L.corr_ring_read.argtypes = [P, P, I32, ctypes.POINTER(I64)]
+        L.corr_dump_bytes.argtypes = [P, I32, ctypes.POINTER(ctypes.c_size_t)]
+        L.corr_status_str.argtypes = [ctypes.c_int]
+        L.corr_status_str.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name != "corr_status_str":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def corr_status_str(status: int) -> str:
+    return lib().corr_status_str(int(status)).decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != CORR_OK:
+        raise CorrError(status, where)
+
+
+def corr_workspace_bytes(cfg: corr_config) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().corr_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n)), "corr_workspace_bytes")
+    return int(n.value)
+
+
+def corr_create(cfg: corr_config, d_workspace: int, ws_bytes: int, hip_stream: int) -> int:
+    out = ctypes.c_void_p(0)
+    _check(lib().corr_create(ctypes.byref(cfg), ctypes.c_void_p(d_workspace), ws_bytes,
+                             ctypes.c_void_p(hip_stream), ctypes.byref(out)), "corr_create")
+    return int(out.value)
+
+
+def corr_destroy(plan: int) -> None:
+    _check(lib().corr_destroy(ctypes.c_void_p(plan)), "corr_destroy")
+
+
+def corr_channelise(plan: int, d_volt: int, n_blocks: int, first_seq: int, d_spectra_dbg: int = 0) -> None:
+    _check(lib().corr_channelise(ctypes.c_void_p(plan), ctypes.c_void_p(d_volt), n_blocks,
+                                 first_seq & 0xFFFFFFFFFFFFFFFF, ctypes.c_void_p(d_spectra_dbg or None)),
+           "corr_channelise")
+
+
+def corr_seq_reset(plan: int) -> None:
+    _check(lib().corr_seq_reset(ctypes.c_void_p(plan)), "corr_seq_reset")
+
+
+def corr_correlate(plan: int, d_samples: int, n_samples: int, row_stride: int = 0) -> None:
+    _check(lib().corr_correlate(ctypes.c_void_p(plan), ctypes.c_void_p(d_samples or None), n_samples,
+                                row_stride), "corr_correlate")
+
+
+def corr_dump(plan: int, what: int, dst: int, dst_is_device: bool):
+    n = ctypes.c_int64(0)
+    exact = ctypes.c_int32(0)
+    _check(lib().corr_dump(ctypes.c_void_p(plan), what, ctypes.c_void_p(dst), int(bool(dst_is_device)),
+                           ctypes.byref(n), ctypes.byref(exact)), "corr_dump")
+    return int(n.value), bool(exact.value)
+
+
+def corr_ring_read(plan: int, dst: int, dst_is_device: bool) -> int:
+    n = ctypes.c_int64(0)
+    _check(lib().corr_ring_read(ctypes.c_void_p(plan), ctypes.c_void_p(dst), int(bool(dst_is_device)),
+                                ctypes.byref(n)), "corr_ring_read")
+    return int(n.value)
+
+
+def corr_dump_bytes(plan: int, what: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().corr_dump_bytes(ctypes.c_void_p(plan), what, ctypes.byref(n)), "corr_dump_bytes")
+    return int(n.value)

@@ -1,0 +1,79 @@
+// Accumulator maintenance: ordered reduction of K-split partial tiles into the
+// integration accumulator, the FP64 long-run fold, and fills.
+//
+// Fig. 1: the accumulators are read after an interval, divided by the number
+// of updates (left to the caller, who gets the raw sums and the count) and
+// reset.  The long-run fold keeps L += V in FP64 across many integrations.
+#include "common.h"
+#include "launch.h"
+
+namespace corr {
+
+// acc[k] = (accumulate ? acc[k] : 0) + part[0][k] + part[1][k] + ... in that
+// order (integer sums are exact; the fixed order keeps float sums
+// reproducible).  n = number of (re, im) pairs per partial buffer.
+template <typename T2>
+__global__ void reduce_splits_kernel(const T2* __restrict__ part, int64_t n, int n_split,
+                                     T2* __restrict__ acc, int accumulate) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  T2 s = part[k];
+  for (int q = 1; q < n_split; ++q) {
+    const T2 p = part[(int64_t)q * n + k];
+    s.x += p.x;
+    s.y += p.y;
+  }
+  if (accumulate) {
+    const T2 o = acc[k];
+    s.x = o.x + s.x;
+    s.y = o.y + s.y;
+  }
+  acc[k] = s;
+}
+
+// L[k] += (double) V[k] over n scalars (the (re, im) pairs flattened).
+template <typename T>
+__global__ void fold_f64_kernel(double* __restrict__ L, const T* __restrict__ V, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) L[k] += (double)V[k];
+}
+
+__global__ void fill_zero_kernel(uint4* __restrict__ p, int64_t n16) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n16) p[k] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+hipError_t launch_reduce_splits(const void* part, int64_t n_pairs, int n_split, void* acc, int accumulate,
+                                bool is_int, hipStream_t s) {
+  if (n_pairs <= 0) return hipSuccess;
+  if (is_int)
+    hipLaunchKernelGGL(reduce_splits_kernel<int2>, dim3(grid_for(n_pairs, 256)), dim3(256), 0, s,
+                       static_cast<const int2*>(part), n_pairs, n_split, static_cast<int2*>(acc), accumulate);
+  else
+    hipLaunchKernelGGL(reduce_splits_kernel<float2>, dim3(grid_for(n_pairs, 256)), dim3(256), 0, s,
+                       static_cast<const float2*>(part), n_pairs, n_split, static_cast<float2*>(acc), accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_f64(double* L, const void* V, int64_t n_scalars, bool is_int, hipStream_t s) {
+  if (n_scalars <= 0) return hipSuccess;
+  if (is_int)
+    hipLaunchKernelGGL(fold_f64_kernel<int32_t>, dim3(grid_for(n_scalars, 256)), dim3(256), 0, s, L,
+                       static_cast<const int32_t*>(V), n_scalars);
+  else
+    hipLaunchKernelGGL(fold_f64_kernel<float>, dim3(grid_for(n_scalars, 256)), dim3(256), 0, s, L,
+                       static_cast<const float*>(V), n_scalars);
+  return hipGetLastError();
+}
+
+// Zero `bytes` (a multiple of 16) at a 16-byte aligned device pointer.
+hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s) {
+  const int64_t n16 = bytes / 16;
+  if (n16 <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(n16, 256)), dim3(256), 0, s, static_cast<uint4*>(p), n16);
+  return hipGetLastError();
+}
+
+}  // namespace corr

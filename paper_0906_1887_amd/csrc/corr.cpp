@@ -1,0 +1,431 @@
+// libcorr host side: the C ABI declared in include/corr.h.
+//
+// Plan = validated configuration + views into the caller's workspace:
+//   acc      integration accumulator [n_ch][P][2] (int32 for the int8 engine,
+//            float32 otherwise); "logically zero" after a reset, so the next
+//            X-engine pass stores instead of read-modify-writing
+//   longrun  FP64 long-run accumulator [n_ch][P][2] (optional)
+//   ring     F-stage output [n_ch][n_in][ring_stride] complex int8 (optional)
+//   part     K-split partial tiles [max_split][n_ch][P][2] (small N_I only)
+//   twiddle  W_256^m table for the F-stage (optional)
+// The library never allocates device memory.
+#include "corr.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+#include "launch.h"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kSplitGranule = 64;  // samples; multiple of every engine's K chunk
+constexpr int kMaxSplit = 16;
+constexpr int kTargetItems = 2048;     // workgroups wanted per X-engine launch
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+  size_t acc = 0, acc_bytes = 0;
+  size_t longrun = 0, longrun_bytes = 0;
+  size_t ring = 0, ring_bytes = 0;
+  size_t part = 0, part_bytes = 0;
+  size_t tw = 0, tw_bytes = 0;
+  size_t total = 0;
+  int max_split = 1;
+  int bt = 128;
+  int n_tiles = 0;
+  int64_t ring_stride = 0;
+  int64_t n_products = 0;
+};
+
+int64_t n_products(int64_t n) { return n * (n + 1) / 2; }
+
+corr_status validate(const corr_config* c) {
+  if (!c) return CORR_E_INVAL;
+  if (c->n_inputs < 1 || c->n_inputs > 65536 || c->n_channels < 1) return CORR_E_INVAL;
+  if (c->engine < CORR_X_FP32 || c->engine > CORR_X_F8) return CORR_E_INVAL;
+  if (c->sample_type != CORR_CF32 && c->sample_type != CORR_CI8) return CORR_E_INVAL;
+  if (c->max_abs < 0 || c->max_abs > 127) return CORR_E_INVAL;
+  if (c->engine == CORR_X_F16 || c->engine == CORR_X_F8) return CORR_E_UNSUPPORTED;
+  if (c->engine == CORR_X_I8) {
+    if (c->sample_type != CORR_CI8 && c->fft_size == 0) return CORR_E_INVAL;
+    if (c->max_abs < 1) return CORR_E_INVAL;  // int32 bound needs a declared range
+  }
+  if (c->fft_size != 0) {
+    if (c->fft_size != 2 * c->n_channels) return CORR_E_INVAL;
+    if (c->fft_size != 256) return CORR_E_UNSUPPORTED;
+    if (c->max_abs < 1) return CORR_E_INVAL;
+    if (!(c->requant_scale > 0.0f) || !std::isfinite(c->requant_scale)) return CORR_E_INVAL;
+    if (c->ring_samples < 1) return CORR_E_INVAL;
+  }
+  if (c->ring_samples < 0) return CORR_E_INVAL;
+  return CORR_OK;
+}
+
+Layout layout_of(const corr_config* c) {
+  Layout L;
+  L.n_products = n_products(c->n_inputs);
+  L.bt = c->n_inputs > 64 ? 128 : 64;
+  const int64_t nb = (c->n_inputs + L.bt - 1) / L.bt;
+  L.n_tiles = (int)(nb * (nb + 1) / 2);
+  const int64_t tiles_total = (int64_t)c->n_channels * L.n_tiles;
+  L.max_split = tiles_total >= kTargetItems
+                    ? 1
+                    : (int)std::min<int64_t>(kMaxSplit, (kTargetItems + tiles_total - 1) / tiles_total);
+  const size_t pair_bytes = 8;  // int2 (int8 engine) or float2 (others)
+  size_t off = 0;
+  L.acc = off;
+  L.acc_bytes = (size_t)c->n_channels * L.n_products * pair_bytes;
+  off = align_up(off + L.acc_bytes, kAlign);
+  if (c->fp64_longrun) {
+    L.longrun = off;
+    L.longrun_bytes = (size_t)c->n_channels * L.n_products * 16;
+    off = align_up(off + L.longrun_bytes, kAlign);
+  }
+  if (c->fft_size != 0) {
+    L.ring_stride = (c->ring_samples + 63) / 64 * 64;
+    L.ring = off;
+    L.ring_bytes = (size_t)c->n_channels * c->n_inputs * L.ring_stride * 2;
+    off = align_up(off + L.ring_bytes, kAlign);
+    L.tw = off;
+    L.tw_bytes = (size_t)c->fft_size * sizeof(float2);
+    off = align_up(off + L.tw_bytes, kAlign);
+  }
+  if (L.max_split > 1) {
+    L.part = off;
+    L.part_bytes = (size_t)L.max_split * L.acc_bytes;
+    off = align_up(off + L.part_bytes, kAlign);
+  }
+  L.total = std::max<size_t>(off, kAlign);
+  return L;
+}
+
+}  // namespace
+
+struct corr_plan {
+  corr_config cfg;
+  Layout L;
+  hipStream_t stream;
+  uint8_t* ws;
+  std::vector<float2> tw_host;
+  int64_t n_accum = 0;       // samples in the integration accumulator
+  bool acc_zero = true;      // accumulator logically zero (contents stale)
+  bool error = false;
+  bool seq_valid = false;
+  uint64_t next_seq = 0;
+  int64_t ring_fill = 0;     // samples waiting in the ring
+};
+
+namespace {
+
+corr_status hip_fail(corr_plan* p, hipError_t e) {
+  if (e == hipSuccess) return CORR_OK;
+  p->error = true;
+  return CORR_E_HIP;
+}
+
+void* at(corr_plan* p, size_t off) { return p->ws + off; }
+
+// Launch one X-engine pass over samples [n_ch][n_in][row_stride] (bytes per
+// sample `sb`), n_samples per row, into the plan's accumulator.
+corr_status xengine_pass(corr_plan* p, const void* x, int sb, int64_t n_samples, int64_t row_stride) {
+  const corr_config& c = p->cfg;
+  const Layout& L = p->L;
+  if (n_samples == 0) return CORR_OK;
+  const int64_t n_gran = (n_samples + kSplitGranule - 1) / kSplitGranule;
+  int split = std::min<int64_t>(L.max_split, std::max<int64_t>(1, n_gran / 4));
+  const int64_t gran_per_split = (n_gran + split - 1) / split;
+  split = (int)((n_gran + gran_per_split - 1) / gran_per_split);
+
+  corr::XArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.x = x;
+  a.row_stride_b = row_stride * sb;
+  a.ch_stride_b = (int64_t)c.n_inputs * a.row_stride_b;
+  a.k_bytes = n_samples * sb;
+  a.k_split_bytes = gran_per_split * kSplitGranule * sb;
+  a.n_products = L.n_products;
+  a.n_in = c.n_inputs;
+  a.n_ch = c.n_channels;
+  a.n_tiles = L.n_tiles;
+  a.n_split = split;
+  const int64_t items = (int64_t)c.n_channels * L.n_tiles * split;
+  if (items > 0x7FFFFFFFll / 2) return CORR_E_INVAL;
+  a.n_items = (int32_t)items;
+  a.per_xcd = (int32_t)((items + corr::kNumXcd - 1) / corr::kNumXcd);
+  const bool direct = (split == 1);
+  a.out = direct ? at(p, L.acc) : at(p, L.part);
+  a.out_split_stride = direct ? 0 : (int64_t)c.n_channels * L.n_products;
+  a.accumulate = direct ? (p->acc_zero ? 0 : 1) : 0;
+  const bool aligned = (a.row_stride_b % 16 == 0) && ((reinterpret_cast<uintptr_t>(x) & 15) == 0);
+
+  hipError_t e;
+  const bool is_int = (c.engine == CORR_X_I8);
+  if (c.engine == CORR_X_I8) e = corr::launch_xeng_i8(a, L.bt, aligned, p->stream);
+  else e = corr::launch_xeng_f32(a, sb, L.bt, aligned, p->stream);
+  if (e != hipSuccess) return hip_fail(p, e);
+  if (!direct) {
+    e = corr::launch_reduce_splits(at(p, L.part), (int64_t)c.n_channels * L.n_products, split, at(p, L.acc),
+                                   p->acc_zero ? 0 : 1, is_int, p->stream);
+    if (e != hipSuccess) return hip_fail(p, e);
+  }
+  p->acc_zero = false;
+  return CORR_OK;
+}
+
+// Integer-sample bounds: |Re V|, |Im V| <= 2 max_abs^2 n.
+bool within(const corr_config& c, int64_t n, double limit) {
+  return 2.0 * (double)c.max_abs * (double)c.max_abs * (double)n <= limit;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* corr_status_str(corr_status s) {
+  switch (s) {
+    case CORR_OK: return "ok";
+    case CORR_E_INVAL: return "invalid argument";
+    case CORR_E_WORKSPACE: return "workspace missing, too small or misaligned";
+    case CORR_E_HIP: return "HIP runtime error";
+    case CORR_E_STATE: return "plan in error state or wrong call order";
+    case CORR_E_OVERFLOW: return "accumulation would exceed the exactness/overflow bound";
+    case CORR_E_SEQ: return "sample block sequence gap or duplicate";
+    case CORR_E_BUSY: return "ring buffer full or result not ready";
+    case CORR_E_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+corr_status corr_workspace_bytes(const corr_config* cfg, size_t* bytes) {
+  try {
+    if (!bytes) return CORR_E_INVAL;
+    const corr_status v = validate(cfg);
+    if (v != CORR_OK) return v;
+    *bytes = layout_of(cfg).total;
+    return CORR_OK;
+  } catch (...) {
+    return CORR_E_INVAL;
+  }
+}
+
+corr_status corr_create(const corr_config* cfg, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                        corr_plan** out) {
+  try {
+    if (!out) return CORR_E_INVAL;
+    const corr_status v = validate(cfg);
+    if (v != CORR_OK) return v;
+    const Layout L = layout_of(cfg);
+    if (!d_workspace || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0)
+      return CORR_E_WORKSPACE;
+    corr_plan* p = new (std::nothrow) corr_plan();
+    if (!p) return CORR_E_INVAL;
+    p->cfg = *cfg;
+    p->L = L;
+    p->stream = static_cast<hipStream_t>(hip_stream);
+    p->ws = static_cast<uint8_t*>(d_workspace);
+    hipError_t e = hipSuccess;
+    if (cfg->fp64_longrun) e = corr::launch_fill_zero(at(p, L.longrun), (int64_t)align_up(L.longrun_bytes, 16), p->stream);
+    if (e == hipSuccess && cfg->fft_size != 0) {
+      const int N = cfg->fft_size;
+      p->tw_host.resize(N);
+      for (int m = 0; m < N; ++m) {
+        const double ang = 2.0 * M_PI * (double)m / (double)N;
+        p->tw_host[m] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+      }
+      e = hipMemcpyAsync(at(p, L.tw), p->tw_host.data(), N * sizeof(float2), hipMemcpyHostToDevice, p->stream);
+    }
+    if (e != hipSuccess) {
+      delete p;
+      return CORR_E_HIP;
+    }
+    *out = p;
+    return CORR_OK;
+  } catch (...) {
+    return CORR_E_INVAL;
+  }
+}
+
+corr_status corr_destroy(corr_plan* plan) {
+  delete plan;
+  return CORR_OK;
+}
+
+corr_status corr_seq_reset(corr_plan* p) {
+  if (!p) return CORR_E_INVAL;
+  if (p->error) return CORR_E_STATE;
+  p->seq_valid = false;
+  return CORR_OK;
+}
+
+corr_status corr_channelise(corr_plan* p, const int8_t* d_volt, int64_t n_blocks, uint64_t first_seq,
+                            float* d_spectra_dbg) {
+  try {
+    if (!p) return CORR_E_INVAL;
+    if (p->error) return CORR_E_STATE;
+    const corr_config& c = p->cfg;
+    if (c.fft_size == 0) return CORR_E_STATE;
+    if (n_blocks < 0 || (n_blocks > 0 && !d_volt)) return CORR_E_INVAL;
+    if (p->seq_valid && first_seq != p->next_seq) return CORR_E_SEQ;
+    if (p->ring_fill + n_blocks > c.ring_samples) return CORR_E_BUSY;
+    if (n_blocks > 0) {
+      corr::FStageCall fc;
+      fc.volt = d_volt;
+      fc.twiddle = static_cast<const float2*>(at(p, p->L.tw));
+      fc.ring = static_cast<int8_t*>(at(p, p->L.ring));
+      fc.dbg = d_spectra_dbg;
+      fc.n_blocks = n_blocks;
+      fc.ring_stride = p->L.ring_stride;
+      fc.t_offset = p->ring_fill;
+      fc.n_in = c.n_inputs;
+      fc.scale = c.requant_scale;
+      fc.max_abs = (float)c.max_abs;
+      const hipError_t e = corr::launch_fstage_call(fc, p->stream);
+      if (e != hipSuccess) return hip_fail(p, e);
+    }
+    p->ring_fill += n_blocks;
+    p->seq_valid = true;
+    p->next_seq = first_seq + (uint64_t)n_blocks;
+    return CORR_OK;
+  } catch (...) {
+    return CORR_E_INVAL;
+  }
+}
+
+corr_status corr_correlate(corr_plan* p, const void* d_samples, int64_t n_samples, int64_t row_stride) {
+  try {
+    if (!p) return CORR_E_INVAL;
+    if (p->error) return CORR_E_STATE;
+    const corr_config& c = p->cfg;
+    const void* x;
+    int sb;
+    int64_t n, stride;
+    if (d_samples == nullptr) {
+      if (c.fft_size == 0) return CORR_E_INVAL;
+      x = at(p, p->L.ring);
+      sb = 2;
+      n = p->ring_fill;
+      stride = p->L.ring_stride;
+    } else {
+      if (n_samples < 0 || row_stride < 0) return CORR_E_INVAL;
+      x = d_samples;
+      sb = (c.sample_type == CORR_CI8) ? 2 : 8;
+      n = n_samples;
+      stride = row_stride == 0 ? n_samples : row_stride;
+      if (stride < n) return CORR_E_INVAL;
+      if ((reinterpret_cast<uintptr_t>(x) % (sb == 8 ? 4 : 2)) != 0) return CORR_E_INVAL;
+    }
+    const int64_t total = p->n_accum + n;
+    if (c.max_abs > 0) {
+      if (c.engine == CORR_X_I8 && !within(c, total, 2147483647.0)) return CORR_E_OVERFLOW;
+      if (c.engine == CORR_X_FP32 && !within(c, total, 16777216.0)) return CORR_E_OVERFLOW;
+    }
+    const corr_status s = xengine_pass(p, x, sb, n, stride);
+    if (s != CORR_OK) return s;
+    p->n_accum = total;
+    if (d_samples == nullptr) p->ring_fill = 0;
+    return CORR_OK;
+  } catch (...) {
+    return CORR_E_INVAL;
+  }
+}
+
+corr_status corr_ring_read(corr_plan* p, void* dst, int32_t dst_is_device, int64_t* n_samples_out) {
+  try {
+    if (!p || !dst) return CORR_E_INVAL;
+    if (p->error) return CORR_E_STATE;
+    const corr_config& c = p->cfg;
+    if (c.fft_size == 0) return CORR_E_STATE;
+    const int64_t n = p->ring_fill;
+    const int64_t rows = (int64_t)c.n_channels * c.n_inputs;
+    hipError_t e = hipSuccess;
+    if (n > 0) {
+      e = hipMemcpy2DAsync(dst, (size_t)n * 2, at(p, p->L.ring), (size_t)p->L.ring_stride * 2, (size_t)n * 2,
+                           (size_t)rows, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           p->stream);
+      if (e != hipSuccess) return hip_fail(p, e);
+    }
+    e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(p, e);
+    if (n_samples_out) *n_samples_out = n;
+    return CORR_OK;
+  } catch (...) {
+    return CORR_E_INVAL;
+  }
+}
+
+corr_status corr_dump_bytes(const corr_plan* p, int32_t what, size_t* bytes) {
+  if (!p || !bytes) return CORR_E_INVAL;
+  if (what & CORR_DUMP_LONGRUN) {
+    if (!p->cfg.fp64_longrun) return CORR_E_INVAL;
+    *bytes = p->L.longrun_bytes;
+  } else {
+    *bytes = p->L.acc_bytes;
+  }
+  return CORR_OK;
+}
+
+corr_status corr_dump(corr_plan* p, int32_t what, void* dst, int32_t dst_is_device, int64_t* n_samples_out,
+                      int32_t* exact_out) {
+  try {
+    if (!p) return CORR_E_INVAL;
+    if (p->error) return CORR_E_STATE;
+    const corr_config& c = p->cfg;
+    const Layout& L = p->L;
+    const bool integ = (what & CORR_DUMP_INTEG) != 0;
+    const bool longrun = (what & CORR_DUMP_LONGRUN) != 0;
+    const bool fold = (what & CORR_DUMP_FOLD) != 0;
+    if (what & ~(CORR_DUMP_INTEG | CORR_DUMP_LONGRUN | CORR_DUMP_FOLD | CORR_DUMP_NO_RESET)) return CORR_E_INVAL;
+    if (integ && longrun) return CORR_E_INVAL;
+    if ((integ || longrun) && !dst) return CORR_E_INVAL;
+    if ((longrun || fold) && !c.fp64_longrun) return CORR_E_INVAL;
+    hipError_t e = hipSuccess;
+    const bool is_int = (c.engine == CORR_X_I8);
+    if (fold && !p->acc_zero) {
+      e = corr::launch_fold_f64(static_cast<double*>(at(p, L.longrun)), at(p, L.acc),
+                                (int64_t)c.n_channels * L.n_products * 2, is_int, p->stream);
+      if (e != hipSuccess) return hip_fail(p, e);
+    }
+    const hipMemcpyKind kind = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (integ) {
+      if (p->acc_zero) {
+        if (dst_is_device) {
+          e = (L.acc_bytes % 16 == 0 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0)
+                  ? corr::launch_fill_zero(dst, (int64_t)L.acc_bytes, p->stream)
+                  : hipMemsetAsync(dst, 0, L.acc_bytes, p->stream);
+        }
+      } else {
+        e = hipMemcpyAsync(dst, at(p, L.acc), L.acc_bytes, kind, p->stream);
+      }
+      if (e != hipSuccess) return hip_fail(p, e);
+    }
+    if (longrun) {
+      e = hipMemcpyAsync(dst, at(p, L.longrun), L.longrun_bytes, kind, p->stream);
+      if (e != hipSuccess) return hip_fail(p, e);
+    }
+    e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(p, e);
+    if (integ && p->acc_zero && !dst_is_device) std::memset(dst, 0, L.acc_bytes);
+    if (n_samples_out) *n_samples_out = p->n_accum;
+    if (exact_out) {
+      const bool exact_engine = (c.engine == CORR_X_I8 || c.engine == CORR_X_FP32) && c.max_abs > 0;
+      *exact_out = (integ && exact_engine) || (longrun && exact_engine) ? 1 : 0;
+    }
+    if (!(what & CORR_DUMP_NO_RESET)) {
+      p->acc_zero = true;
+      p->n_accum = 0;
+    }
+    return CORR_OK;
+  } catch (...) {
+    return CORR_E_INVAL;
+  }
+}
+
+}  // extern "C"

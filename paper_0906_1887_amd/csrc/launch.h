@@ -1,0 +1,35 @@
+// Kernel launchers of libcorr (internal; the public interface is corr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace corr {
+
+struct FArgs;
+
+// int8 MFMA X-engine; bt = 64 or 128; aligned: rows and base 16-byte aligned.
+hipError_t launch_xeng_i8(const XArgs& a, int bt, bool aligned, hipStream_t s);
+// FP32 X-engine; sample_bytes = 8 (complex float32) or 2 (complex int8).
+hipError_t launch_xeng_f32(const XArgs& a, int sample_bytes, int bt, bool aligned, hipStream_t s);
+hipError_t launch_reduce_splits(const void* part, int64_t n_pairs, int n_split, void* acc, int accumulate,
+                                bool is_int, hipStream_t s);
+hipError_t launch_fold_f64(double* L, const void* V, int64_t n_scalars, bool is_int, hipStream_t s);
+hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
+
+struct FStageCall {
+  const int8_t* volt;
+  const float2* twiddle;
+  int8_t* ring;
+  float* dbg;
+  int64_t n_blocks;
+  int64_t ring_stride;
+  int64_t t_offset;
+  int32_t n_in;
+  float scale;
+  float max_abs;
+};
+hipError_t launch_fstage_call(const FStageCall& c, hipStream_t s);
+
+}  // namespace corr

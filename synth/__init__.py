@@ -37,6 +37,8 @@ __all__ = [
     "counter",
     "ci8",
     "ci8_channel",
+    "ci8_channel_numpy",
+    "ci8_block",
     "real_voltages",
     "complex_float",
     "coherent_pairs",
@@ -113,13 +115,10 @@ def _levels(u32: np.ndarray, thr: np.ndarray, max_abs: int) -> np.ndarray:
     return lv.astype(np.int8)
 
 
-def ci8_channel(seed: int, ch: int, n_inputs: int, n_samples: int,
-                sigma: float = 2.0, max_abs: int = 7, t0: int = 0,
-                inputs=None) -> np.ndarray:
-    """One channel of ``ci8``: int8 array [n_inputs][n_samples][2] (re, im).
-
-    ``inputs`` optionally selects a subset of input indices (the row order
-    of the result follows it)."""
+def ci8_channel_numpy(seed: int, ch: int, n_inputs: int, n_samples: int,
+                      sigma: float = 2.0, max_abs: int = 7, t0: int = 0,
+                      inputs=None) -> np.ndarray:
+    """numpy form of ``ci8_channel`` (slow; the reference the C twin is tested against)."""
     if n_samples + t0 > (1 << T_BITS) or ch >= (1 << CH_BITS) or n_inputs > (1 << IN_BITS):
         raise ValueError("counter field overflow")
     thr = level_thresholds(sigma, max_abs)
@@ -133,13 +132,63 @@ def ci8_channel(seed: int, ch: int, n_inputs: int, n_samples: int,
     return out
 
 
+_host = None
+HOST_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsynth_host.so")
+HOST_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "synth_host.c")
+
+
+def build_host() -> str:
+    import subprocess
+    tmp = HOST_LIB + ".tmp"
+    subprocess.run(["gcc", "-std=c99", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, HOST_SRC], check=True)
+    os.replace(tmp, HOST_LIB)
+    return HOST_LIB
+
+
+def _host_lib():
+    global _host
+    if _host is None:
+        if not os.path.exists(HOST_LIB):
+            build_host()
+        L = ctypes.CDLL(HOST_LIB)
+        P, I64 = ctypes.c_void_p, ctypes.c_int64
+        L.synth_ci8_host.argtypes = [P, I64, I64, P, I64, I64, I64, ctypes.c_uint64, P, ctypes.c_int, ctypes.c_int]
+        L.synth_ci8_host.restype = None
+        _host = L
+    return _host
+
+
+def ci8_block(seed: int, ch0: int, n_channels: int, n_inputs: int, n_samples: int,
+              sigma: float = 2.0, max_abs: int = 7, t0: int = 0, inputs=None) -> np.ndarray:
+    """Channels ch0 .. ch0+n_channels-1: int8 [n_channels][rows][n_samples][2]
+    (rows = all n_inputs, or the selected ``inputs``), by the C twin."""
+    if n_samples + t0 > (1 << T_BITS) or ch0 + n_channels > (1 << CH_BITS) or n_inputs > (1 << IN_BITS):
+        raise ValueError("counter field overflow")
+    thr = level_thresholds(sigma, max_abs)
+    rows = None if inputs is None else np.ascontiguousarray(inputs, dtype=np.int32)
+    n_rows = n_inputs if rows is None else rows.size
+    out = np.empty((n_channels, n_rows, n_samples, 2), dtype=np.int8)
+    if out.size:
+        _host_lib().synth_ci8_host(out.ctypes.data, ch0, n_channels,
+                                   None if rows is None else rows.ctypes.data, n_rows, t0, n_samples,
+                                   seed & 0xFFFFFFFFFFFFFFFF, thr.ctypes.data, thr.size, max_abs)
+    return out
+
+
+def ci8_channel(seed: int, ch: int, n_inputs: int, n_samples: int,
+                sigma: float = 2.0, max_abs: int = 7, t0: int = 0,
+                inputs=None) -> np.ndarray:
+    """One channel of ``ci8``: int8 array [n_inputs][n_samples][2] (re, im).
+
+    ``inputs`` optionally selects a subset of input indices (the row order
+    of the result follows it)."""
+    return ci8_block(seed, ch, 1, n_inputs, n_samples, sigma, max_abs, t0, inputs)[0]
+
+
 def ci8(seed: int, n_channels: int, n_inputs: int, n_samples: int,
         sigma: float = 2.0, max_abs: int = 7) -> np.ndarray:
     """All channels: int8 [n_channels][n_inputs][n_samples][2]."""
-    out = np.empty((n_channels, n_inputs, n_samples, 2), dtype=np.int8)
-    for c in range(n_channels):
-        out[c] = ci8_channel(seed, c, n_inputs, n_samples, sigma, max_abs)
-    return out
+    return ci8_block(seed, 0, n_channels, n_inputs, n_samples, sigma, max_abs)
 
 
 # ---------------------------------------------------------------------------
@@ -214,6 +263,21 @@ def complex_float(seed: int, ch: int, n_inputs: int, n_samples: int,
 # ---------------------------------------------------------------------------
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsynth.so")
+
+
+def build() -> str:
+    """Compile libsynth.so (the device generator) for gfx950 with hipcc."""
+    import subprocess
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tmp = LIB_PATH + ".tmp"
+    cmd = [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-x", "hip", os.path.join(_HERE, "synth_dev.hip"), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for synth_dev.hip:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
 
 
 class _Thr(ctypes.Structure):

@@ -1,0 +1,118 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+entry point the header declares, validates configurations and refuses
+overflowing accumulations before any launch."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "corr.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(corr_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_header_symbols_exported():
+    from paper_0906_1887_amd import _lib
+    L = _lib.lib()
+    names = _declared()
+    assert "corr_create" in names and "corr_correlate" in names and "corr_dump" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.EXPORTED)
+
+
+def _cfg(**kw):
+    from paper_0906_1887_amd import make_config
+    return make_config(**kw)
+
+
+def test_workspace_and_validation():
+    from paper_0906_1887_amd import _lib
+    ws = _lib.corr_workspace_bytes(_cfg(n_inputs=1024, n_channels=768, engine="i8"))
+    assert ws >= 768 * 524800 * 8
+    small = _lib.corr_workspace_bytes(_cfg(n_inputs=64, n_channels=128, engine="i8"))
+    assert small > 128 * 2080 * 8        # includes K-split partials at small N_I
+    fx = _lib.corr_workspace_bytes(_cfg(n_inputs=64, n_channels=128, engine="i8", fft_size=256,
+                                        requant_scale=0.011, ring_samples=10000, fp64_longrun=True))
+    assert fx >= 128 * 2080 * (8 + 16) + 128 * 64 * 10000 * 2
+    bad = [
+        dict(n_inputs=0, n_channels=4),
+        dict(n_inputs=4, n_channels=0),
+        dict(n_inputs=4, n_channels=4, engine="i8", sample_type="cf32"),
+        dict(n_inputs=4, n_channels=4, engine="i8", max_abs=0),
+        dict(n_inputs=4, n_channels=64, fft_size=256, requant_scale=0.1, ring_samples=10),
+        dict(n_inputs=4, n_channels=128, fft_size=256, requant_scale=0.0, ring_samples=10),
+        dict(n_inputs=4, n_channels=128, fft_size=256, requant_scale=0.1, ring_samples=0),
+    ]
+    for kw in bad:
+        with pytest.raises(_lib.CorrError) as e:
+            _lib.corr_workspace_bytes(_cfg(**kw))
+        assert e.value.status == _lib.CORR_E_INVAL, kw
+    for kw in (dict(n_inputs=4, n_channels=64, fft_size=128, requant_scale=0.1, ring_samples=10),
+               dict(n_inputs=4, n_channels=4, engine="f16", sample_type="cf32", max_abs=0)):
+        with pytest.raises(_lib.CorrError) as e:
+            _lib.corr_workspace_bytes(_cfg(**kw))
+        assert e.value.status == _lib.CORR_E_UNSUPPORTED, kw
+
+
+def test_create_rejects_bad_workspace():
+    from paper_0906_1887_amd import _lib
+    cfg = _cfg(n_inputs=16, n_channels=2, engine="i8")
+    n = _lib.corr_workspace_bytes(cfg)
+    for ptr, size in ((0, n), (0x1000_0000_0100 + 16, n), (0x1000_0000_0000, n - 1)):
+        with pytest.raises(_lib.CorrError) as e:
+            _lib.corr_create(cfg, ptr, size, 0)
+        assert e.value.status == _lib.CORR_E_WORKSPACE
+
+
+def _gpu_visible() -> bool:
+    import torch
+    return torch.cuda.device_count() > 0
+
+
+@pytest.mark.skipif(_gpu_visible(), reason="uses a fake device pointer; host-only check")
+def test_host_checks_before_launch():
+    """A plan with neither F-stage nor long-run queues no device work at
+    creation, so its host-side refusals can be exercised without a GPU (the
+    workspace pointer is never dereferenced; skipped where a GPU is visible)."""
+    from paper_0906_1887_amd import _lib
+    fake = 0x7F00_0000_0000
+    cfg = _cfg(n_inputs=16, n_channels=2, engine="i8", max_abs=7)
+    plan = _lib.corr_create(cfg, fake, _lib.corr_workspace_bytes(cfg), 0)
+    try:
+        # 2*49*n > 2^31-1 for n >= 21_913_099 samples: refused before launch
+        with pytest.raises(_lib.CorrError) as e:
+            _lib.corr_correlate(plan, fake, 21_913_099, 0)
+        assert e.value.status == _lib.CORR_E_OVERFLOW
+        with pytest.raises(_lib.CorrError) as e:
+            _lib.corr_channelise(plan, fake, 1, 0)
+        assert e.value.status == _lib.CORR_E_STATE          # no F-stage in this plan
+        with pytest.raises(_lib.CorrError) as e:
+            _lib.corr_correlate(plan, fake, 10, 5)           # row stride < n
+        assert e.value.status == _lib.CORR_E_INVAL
+        with pytest.raises(_lib.CorrError) as e:
+            _lib.corr_correlate(plan, fake + 1, 10, 0)       # misaligned int8 pairs
+        assert e.value.status == _lib.CORR_E_INVAL
+        assert _lib.corr_dump_bytes(plan, _lib.CORR_DUMP_INTEG) == 2 * 136 * 8
+    finally:
+        _lib.corr_destroy(plan)
+    cfg = _cfg(n_inputs=16, n_channels=2, engine="fp32", sample_type="ci8", max_abs=7)
+    plan = _lib.corr_create(cfg, fake, _lib.corr_workspace_bytes(cfg), 0)
+    try:
+        with pytest.raises(_lib.CorrError) as e:            # FP32 exactness bound 2^24
+            _lib.corr_correlate(plan, fake, 171_200, 0)
+        assert e.value.status == _lib.CORR_E_OVERFLOW
+    finally:
+        _lib.corr_destroy(plan)
+
+
+def test_status_strings():
+    from paper_0906_1887_amd import _lib
+    for s in range(-8, 1):
+        assert _lib.corr_status_str(s) and "unknown" not in _lib.corr_status_str(s)

@@ -50,3 +50,13 @@ def test_complex_float_gains_pairs():
     i, j = pairs[0]
     r = np.mean(z[i] * np.conj(z[j])) / (g[i] * g[j])
     assert abs(r - 0.1) < 0.05
+
+
+def test_c_twin_matches_numpy():
+    for args in ((5, 7, 10, 100), (0, 0, 1, 1), (123456789, 1000, 33, 257)):
+        assert np.array_equal(synth.ci8_channel(*args), synth.ci8_channel_numpy(*args))
+    assert np.array_equal(synth.ci8_channel(5, 7, 10, 60, t0=40, inputs=[3, 9]),
+                          synth.ci8_channel_numpy(5, 7, 10, 60, t0=40, inputs=[3, 9]))
+    blk = synth.ci8_block(2, 3, 4, 6, 50)
+    for c in range(4):
+        assert np.array_equal(blk[c], synth.ci8_channel_numpy(2, 3 + c, 6, 50))
