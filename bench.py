@@ -61,6 +61,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-channels", type=int, default=16)
+    ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
+                    help="copy: only a 1 GiB device-to-device copy, the known-size reference for "
+                         "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -68,6 +71,16 @@ def main() -> int:
         return 2
 
     import torch
+
+    if args.mode == "copy":
+        a = torch.ones(1 << 30, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read": 1 << 30, "bytes_written": 1 << 30, "copies": 3}))
+        return 0
 
     import synth
     from paper_0906_1887_amd import Correlator, perfmodel

@@ -136,7 +136,8 @@ corr_status corr_seq_reset(corr_plan *plan);
  * [row_stride] (row_stride in samples; 0 means n_samples), of which the first
  * n_samples of each row are used.  d_samples == NULL correlates the samples
  * the F-stage has put in the ring (n_samples and row_stride are then
- * ignored) and empties the ring.
+ * ignored) and empties the ring; on a plan without an F-stage, NULL is
+ * accepted only with n_samples == 0 (an empty pass, nothing is done).
  * CORR_E_OVERFLOW (before any launch) if, for integer samples, the samples
  * accumulated since the last reset would exceed 2*max_abs^2*n <= 2^31-1 with
  * the int32 engine, or 2^24 with the FP32 engine on integer data (exact FP32

@@ -307,8 +307,11 @@ corr_status corr_correlate(corr_plan* p, const void* d_samples, int64_t n_sample
     const void* x;
     int sb;
     int64_t n, stride;
+    if (d_samples == nullptr && c.fft_size == 0) {
+      // No ring to drain: only an empty pass (n_samples == 0) is meaningful.
+      return n_samples == 0 ? CORR_OK : CORR_E_INVAL;
+    }
     if (d_samples == nullptr) {
-      if (c.fft_size == 0) return CORR_E_INVAL;
       x = at(p, p->L.ring);
       sb = 2;
       n = p->ring_fill;
