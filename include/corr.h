@@ -68,9 +68,13 @@ typedef enum {
 typedef enum {
     CORR_X_FP32 = 0,          /* plain FP32 vector FMA, FP32 accumulation  */
     CORR_X_I8 = 1,            /* int8 MFMA, int32 accumulation (CI8 only)  */
-    CORR_X_F16 = 2,           /* FP16 MFMA, FP32 accumulation (CF32 input) */
-    CORR_X_F8 = 3             /* OCP FP8 E4M3 MFMA with a power-of-two
-                                 per-channel scale, FP32 accumulation     */
+    CORR_X_F16 = 2,           /* FP16 MFMA, FP32 accumulation (CF32 input,
+                                 staged unscaled, |x| < 65504)             */
+    CORR_X_F8 = 3             /* OCP FP8 E4M3 MFMA, FP32 accumulation (CF32
+                                 input staged with a power-of-two per-channel
+                                 scale s_c: the largest with s_c * max|x| <=
+                                 448, kept in [2^-60, 2^60]; the epilogue
+                                 multiplies by 1/s_c^2)                    */
 } corr_engine_t;
 
 typedef struct {
@@ -172,8 +176,83 @@ corr_status corr_dump(corr_plan *plan, int32_t what, void *dst, int32_t dst_is_d
  * output.  Synchronises the plan's stream. */
 corr_status corr_ring_read(corr_plan *plan, void *dst, int32_t dst_is_device, int64_t *n_samples_out);
 
+/* FP16 / FP8 engines: copy the last chunk staged by corr_correlate to host
+ * dst as dense [n_channels][n_inputs][n][2] elements (binary16, or E4M3
+ * bytes), n = *n_samples_out, and, if scales != NULL, the per-channel FP8
+ * scales s_c (1 for FP16) to host scales[n_channels].  dst must hold
+ * n_channels * n_inputs * ring_samples * 2 elements.  For parity tests of the
+ * conversion.  Synchronises the plan's stream. */
+corr_status corr_stage_read(corr_plan *plan, void *dst, float *scales, int64_t *n_samples_out);
+
 /* Bytes of one integration dump (what = CORR_DUMP_INTEG) or long-run dump. */
 corr_status corr_dump_bytes(const corr_plan *plan, int32_t what, size_t *bytes);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of integration jobs.
+ *
+ * Jobs from streams with different input and channel counts arrive at any
+ * time (the real-time operation of Sec. 5; the batching of many cycles per
+ * GPU call, Sec. 5).  corr_sched_submit never blocks: a job waits in a FIFO
+ * queue until its HBM footprint (its samples, unless the caller supplies them
+ * on the device, plus its plan workspace) fits in the caller's arena, then it
+ * is admitted onto one of n_streams HIP streams, where it runs concurrently
+ * with the other admitted jobs: samples are produced by the job's fill
+ * callback (or read from the caller's buffer), correlated by the int8
+ * X-engine (the job's plan), and the integration is copied to the job's
+ * result buffer.  The job is complete when that copy has landed (the latency
+ * end point); its arena region is then reused.  A job whose footprint exceeds the whole arena is refused at
+ * submission (CORR_E_WORKSPACE).
+ * ------------------------------------------------------------------------ */
+typedef struct corr_sched corr_sched;
+
+/* Writes the job's samples, complex int8 [n_channels][n_inputs][n_samples],
+ * to device memory d_samples by queueing work on hip_stream; called from the
+ * scheduler's thread when the job is admitted; must not block. */
+typedef void (*corr_fill_fn)(void *user, uint64_t job_id, void *d_samples, int64_t n_channels,
+                             int64_t n_inputs, int64_t n_samples, void *hip_stream);
+
+typedef struct {
+    int32_t n_inputs;         /* N_I >= 1                                     */
+    int32_t n_channels;       /* N_C >= 1                                     */
+    int64_t n_samples;        /* time samples per channel, >= 1               */
+    int32_t max_abs;          /* declared bound on |re|, |im| (1..127)        */
+    int32_t reserved;
+    corr_fill_fn fill;        /* produces the samples on the device, or NULL  */
+    void *fill_user;          /* passed to fill                                */
+    const void *d_samples;    /* used when fill == NULL: caller's device
+                                 samples, valid until the job completes       */
+    void *dst;                /* int32 [n_channels][P][2] result, valid until
+                                 the job completes                            */
+    int32_t dst_is_device;    /* 1: dst is device memory; 0: host memory
+                                 (pinned, else the copy blocks the scheduler) */
+    int32_t reserved2;
+} corr_job_desc;
+
+/* Seconds on the clock the scheduler stamps completions with (monotonic). */
+double corr_sched_now(void);
+
+/* d_arena: caller-owned device memory (256-byte aligned) the scheduler carves
+ * job footprints from; n_streams: concurrent jobs (1..16; streams of default
+ * priority created and owned by the scheduler). */
+corr_status corr_sched_create(void *d_arena, size_t arena_bytes, int32_t n_streams, corr_sched **out);
+
+/* Queue a job.  t_arrival: its arrival time on corr_sched_now()'s clock (the
+ * latency origin).  *job_id receives its id.  Never blocks. */
+corr_status corr_sched_submit(corr_sched *s, const corr_job_desc *job, double t_arrival, uint64_t *job_id);
+
+/* CORR_E_BUSY while job_id is queued or running.  Once it is complete:
+ * CORR_OK (or the job's own error status), *n_samples_out, *t_admit and
+ * *t_done (its admission and completion times) are written and the job
+ * record is released; a second poll of the same id gives CORR_E_INVAL. */
+corr_status corr_sched_poll(corr_sched *s, uint64_t job_id, int64_t *n_samples_out, double *t_admit,
+                            double *t_done);
+
+/* stats[0..7] = submitted, admitted, completed, failed, queued now, running
+ * now, peak arena bytes in use, arena bytes. */
+corr_status corr_sched_stats(corr_sched *s, int64_t stats[8]);
+
+/* Wait for every queued and running job, then free the scheduler. */
+corr_status corr_sched_destroy(corr_sched *s);
 
 /* Static description of a status code. */
 const char *corr_status_str(corr_status s);

@@ -11,11 +11,15 @@ from . import _lib
 from ._lib import (CORR_CF32, CORR_CI8, CORR_DUMP_FOLD, CORR_DUMP_INTEG, CORR_DUMP_LONGRUN,
                    CORR_DUMP_NO_RESET, CORR_X_F8, CORR_X_F16, CORR_X_FP32, CORR_X_I8, CorrError,
                    corr_channelise, corr_config, corr_correlate, corr_create, corr_destroy, corr_dump,
-                   corr_dump_bytes, corr_ring_read, corr_seq_reset, corr_status_str, corr_workspace_bytes)
+                   corr_dump_bytes, corr_job_desc, corr_ring_read, corr_sched_create, corr_sched_destroy,
+                   corr_sched_now, corr_sched_poll, corr_sched_stats, corr_sched_submit, corr_seq_reset,
+                   corr_stage_read, corr_status_str, corr_workspace_bytes)
 
 __all__ = [
     "Correlator", "CorrError", "corr_config", "corr_workspace_bytes", "corr_create", "corr_destroy",
-    "corr_channelise", "corr_seq_reset", "corr_correlate", "corr_dump", "corr_ring_read", "corr_dump_bytes",
+    "corr_channelise", "corr_seq_reset", "corr_correlate", "corr_dump", "corr_ring_read", "corr_stage_read",
+    "corr_dump_bytes", "corr_job_desc", "corr_sched_now", "corr_sched_create", "corr_sched_submit",
+    "corr_sched_poll", "corr_sched_stats", "corr_sched_destroy", "Scheduler",
     "corr_status_str", "ENGINES", "SAMPLE_TYPES",
 ]
 
@@ -112,6 +116,17 @@ class Correlator:
         flat = buf.reshape(-1)[: self.n_channels * self.n_inputs * n * 2]
         return flat.reshape(self.n_channels, self.n_inputs, n, 2)
 
+    def stage_read(self):
+        """FP16/FP8 engines: (staged elements [n_ch][n_in][n][2] as a numpy
+        uint16/uint8 array, per-channel scales) of the last staged chunk."""
+        import numpy as np
+        esz = 2 if self.engine == "f16" else 1
+        dt = np.uint16 if esz == 2 else np.uint8
+        buf = np.empty(self.n_channels * self.n_inputs * max(1, self.cfg.ring_samples) * 2, dtype=dt)
+        sc = np.empty(self.n_channels, dtype=np.float32)
+        n = corr_stage_read(self.plan, buf.ctypes.data, sc.ctypes.data)
+        return buf[: self.n_channels * self.n_inputs * n * 2].reshape(self.n_channels, self.n_inputs, n, 2), sc
+
     def seq_reset(self) -> None:
         corr_seq_reset(self.plan)
 
@@ -119,6 +134,55 @@ class Correlator:
         if getattr(self, "plan", 0):
             corr_destroy(self.plan)
             self.plan = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Scheduler:
+    """Serving scheduler over a device arena (torch tensor) with n_streams
+    concurrent jobs.  ``submit`` takes the job shape, a fill callback address
+    (a C function pointer of type corr_fill_fn) with its user pointer, or
+    device samples, and a result tensor (device, or pinned host); ``poll``
+    returns None until the job's result has landed there."""
+
+    def __init__(self, arena_bytes: int, n_streams: int = 4, device: str = "cuda:0"):
+        import torch
+
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=device)
+        self.handle = corr_sched_create(self.arena.data_ptr(), arena_bytes, n_streams)
+
+    @staticmethod
+    def now() -> float:
+        return corr_sched_now()
+
+    def submit(self, n_inputs: int, n_channels: int, n_samples: int, dst, max_abs: int = 7,
+               fill: int = 0, fill_user: int = 0, d_samples: int = 0, t_arrival: float | None = None) -> int:
+        j = corr_job_desc()
+        j.n_inputs = n_inputs
+        j.n_channels = n_channels
+        j.n_samples = n_samples
+        j.max_abs = max_abs
+        j.fill = fill or None
+        j.fill_user = fill_user or None
+        j.d_samples = d_samples or None
+        j.dst = dst.data_ptr()
+        j.dst_is_device = int(dst.device.type == "cuda")
+        return corr_sched_submit(self.handle, j, corr_sched_now() if t_arrival is None else t_arrival)
+
+    def poll(self, job_id: int):
+        return corr_sched_poll(self.handle, job_id)
+
+    def stats(self):
+        return corr_sched_stats(self.handle)
+
+    def close(self) -> None:
+        if getattr(self, "handle", 0):
+            corr_sched_destroy(self.handle)
+            self.handle = 0
 
     def __del__(self):
         try:

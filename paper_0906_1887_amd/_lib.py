@@ -34,7 +34,9 @@ CORR_DUMP_NO_RESET = 8
 
 EXPORTED = [
     "corr_workspace_bytes", "corr_create", "corr_destroy", "corr_channelise", "corr_seq_reset",
-    "corr_correlate", "corr_dump", "corr_ring_read", "corr_dump_bytes", "corr_status_str",
+    "corr_correlate", "corr_dump", "corr_ring_read", "corr_stage_read", "corr_dump_bytes", "corr_status_str",
+    "corr_sched_now", "corr_sched_create", "corr_sched_submit", "corr_sched_poll", "corr_sched_stats",
+    "corr_sched_destroy",
 ]
 
 
@@ -49,6 +51,22 @@ class corr_config(ctypes.Structure):
         ("requant_scale", ctypes.c_float),
         ("fp64_longrun", ctypes.c_int32),
         ("ring_samples", ctypes.c_int64),
+    ]
+
+
+class corr_job_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_inputs", ctypes.c_int32),
+        ("n_channels", ctypes.c_int32),
+        ("n_samples", ctypes.c_int64),
+        ("max_abs", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("fill", ctypes.c_void_p),
+        ("fill_user", ctypes.c_void_p),
+        ("d_samples", ctypes.c_void_p),
+        ("dst", ctypes.c_void_p),
+        ("dst_is_device", ctypes.c_int32),
+        ("reserved2", ctypes.c_int32),
     ]
 
 
@@ -79,12 +97,21 @@ def lib():
         L.corr_correlate.argtypes = [P, P, I64, I64]
         L.corr_dump.argtypes = [P, I32, P, I32, ctypes.POINTER(I64), ctypes.POINTER(I32)]
         L.corr_ring_read.argtypes = [P, P, I32, ctypes.POINTER(I64)]
+        L.corr_stage_read.argtypes = [P, P, P, ctypes.POINTER(I64)]
         L.corr_dump_bytes.argtypes = [P, I32, ctypes.POINTER(ctypes.c_size_t)]
         L.corr_status_str.argtypes = [ctypes.c_int]
         L.corr_status_str.restype = ctypes.c_char_p
+        L.corr_sched_now.argtypes = []
+        L.corr_sched_create.argtypes = [P, ctypes.c_size_t, I32, ctypes.POINTER(P)]
+        L.corr_sched_submit.argtypes = [P, ctypes.POINTER(corr_job_desc), ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]
+        L.corr_sched_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]
+        L.corr_sched_stats.argtypes = [P, ctypes.POINTER(I64)]
+        L.corr_sched_destroy.argtypes = [P]
         for name in EXPORTED:
-            if name != "corr_status_str":
+            if name not in ("corr_status_str", "corr_sched_now"):
                 getattr(L, name).restype = ctypes.c_int
+        L.corr_sched_now.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -145,7 +172,56 @@ def corr_ring_read(plan: int, dst: int, dst_is_device: bool) -> int:
     return int(n.value)
 
 
+def corr_stage_read(plan: int, dst: int, scales: int = 0) -> int:
+    n = ctypes.c_int64(0)
+    _check(lib().corr_stage_read(ctypes.c_void_p(plan), ctypes.c_void_p(dst), ctypes.c_void_p(scales or None),
+                                 ctypes.byref(n)), "corr_stage_read")
+    return int(n.value)
+
+
 def corr_dump_bytes(plan: int, what: int) -> int:
     n = ctypes.c_size_t(0)
     _check(lib().corr_dump_bytes(ctypes.c_void_p(plan), what, ctypes.byref(n)), "corr_dump_bytes")
     return int(n.value)
+
+
+def corr_sched_now() -> float:
+    return float(lib().corr_sched_now())
+
+
+def corr_sched_create(d_arena: int, arena_bytes: int, n_streams: int) -> int:
+    out = ctypes.c_void_p(0)
+    _check(lib().corr_sched_create(ctypes.c_void_p(d_arena), arena_bytes, n_streams, ctypes.byref(out)),
+           "corr_sched_create")
+    return int(out.value)
+
+
+def corr_sched_submit(sched: int, job: corr_job_desc, t_arrival: float) -> int:
+    jid = ctypes.c_uint64(0)
+    _check(lib().corr_sched_submit(ctypes.c_void_p(sched), ctypes.byref(job), t_arrival, ctypes.byref(jid)),
+           "corr_sched_submit")
+    return int(jid.value)
+
+
+def corr_sched_poll(sched: int, job_id: int):
+    """None while the job is queued or running; else (status, n_samples, t_admit, t_done)."""
+    n = ctypes.c_int64(0)
+    ta = ctypes.c_double(0.0)
+    td = ctypes.c_double(0.0)
+    st = lib().corr_sched_poll(ctypes.c_void_p(sched), job_id, ctypes.byref(n), ctypes.byref(ta), ctypes.byref(td))
+    if st == CORR_E_BUSY:
+        return None
+    if st == CORR_E_INVAL:
+        raise CorrError(st, "corr_sched_poll")
+    return int(st), int(n.value), float(ta.value), float(td.value)
+
+
+def corr_sched_stats(sched: int):
+    arr = (ctypes.c_int64 * 8)()
+    _check(lib().corr_sched_stats(ctypes.c_void_p(sched), arr), "corr_sched_stats")
+    keys = ["submitted", "admitted", "completed", "failed", "queued", "running", "peak_arena_bytes", "arena_bytes"]
+    return dict(zip(keys, [int(v) for v in arr]))
+
+
+def corr_sched_destroy(sched: int) -> None:
+    _check(lib().corr_sched_destroy(ctypes.c_void_p(sched)), "corr_sched_destroy")

@@ -13,6 +13,11 @@ namespace corr {
 // which re-read the same input rows) runs on one XCD, in order.
 constexpr int kNumXcd = 8;
 
+// Element kinds of the matrix-core X-engine.
+constexpr int kElemI8 = 0;
+constexpr int kElemF16 = 1;
+constexpr int kElemF8 = 2;
+
 __device__ __forceinline__ int64_t xcd_item(int64_t bid, int64_t per_xcd) {
   const int64_t xcd = bid % kNumXcd;
   const int64_t slot = bid / kNumXcd;
@@ -48,6 +53,7 @@ struct XArgs {
   int32_t per_xcd;          // ceil(n_items / 8)
   int32_t accumulate;       // 1: out += tile; 0: out = tile
   int32_t pad_;
+  const float* inv_scale2;  // FP8: per-channel 1/s_c^2 applied in the epilogue (else null)
 };
 
 }  // namespace corr

@@ -21,6 +21,7 @@
 
 #include "common.h"
 #include "launch.h"
+#include "plan_internal.h"
 
 namespace {
 
@@ -37,6 +38,10 @@ struct Layout {
   size_t ring = 0, ring_bytes = 0;
   size_t part = 0, part_bytes = 0;
   size_t tw = 0, tw_bytes = 0;
+  size_t stage = 0, stage_bytes = 0;   // FP16/FP8 staged samples
+  size_t mbits = 0, scales = 0;        // FP8 per-channel max and 1/s^2
+  int64_t stage_stride = 0;            // staged samples per row
+  int stage_sb = 0;                    // staged bytes per complex sample
   size_t total = 0;
   int max_split = 1;
   int bt = 128;
@@ -53,7 +58,12 @@ corr_status validate(const corr_config* c) {
   if (c->engine < CORR_X_FP32 || c->engine > CORR_X_F8) return CORR_E_INVAL;
   if (c->sample_type != CORR_CF32 && c->sample_type != CORR_CI8) return CORR_E_INVAL;
   if (c->max_abs < 0 || c->max_abs > 127) return CORR_E_INVAL;
-  if (c->engine == CORR_X_F16 || c->engine == CORR_X_F8) return CORR_E_UNSUPPORTED;
+  if (c->engine == CORR_X_F16 || c->engine == CORR_X_F8) {
+    // float samples staged to FP16 / FP8 in chunks of ring_samples
+    if (c->sample_type != CORR_CF32 || c->max_abs != 0 || c->fft_size != 0) return CORR_E_INVAL;
+    if (c->ring_samples < 1) return CORR_E_INVAL;
+    if (c->n_channels > 65535) return CORR_E_UNSUPPORTED;
+  }
   if (c->engine == CORR_X_I8) {
     if (c->sample_type != CORR_CI8 && c->fft_size == 0) return CORR_E_INVAL;
     if (c->max_abs < 1) return CORR_E_INVAL;  // int32 bound needs a declared range
@@ -98,6 +108,17 @@ Layout layout_of(const corr_config* c) {
     L.tw_bytes = (size_t)c->fft_size * sizeof(float2);
     off = align_up(off + L.tw_bytes, kAlign);
   }
+  if (c->engine == CORR_X_F16 || c->engine == CORR_X_F8) {
+    L.stage_sb = (c->engine == CORR_X_F16) ? 4 : 2;
+    L.stage_stride = (c->ring_samples + 63) / 64 * 64;
+    L.stage = off;
+    L.stage_bytes = (size_t)c->n_channels * c->n_inputs * L.stage_stride * L.stage_sb;
+    off = align_up(off + L.stage_bytes, kAlign);
+    L.mbits = off;
+    off = align_up(off + (size_t)c->n_channels * 4, kAlign);
+    L.scales = off;
+    off = align_up(off + (size_t)c->n_channels * 4, kAlign);
+  }
   if (L.max_split > 1) {
     L.part = off;
     L.part_bytes = (size_t)L.max_split * L.acc_bytes;
@@ -121,6 +142,7 @@ struct corr_plan {
   bool seq_valid = false;
   uint64_t next_seq = 0;
   int64_t ring_fill = 0;     // samples waiting in the ring
+  int64_t stage_fill = 0;    // samples of the last FP16/FP8 staged chunk
 };
 
 namespace {
@@ -135,7 +157,8 @@ void* at(corr_plan* p, size_t off) { return p->ws + off; }
 
 // Launch one X-engine pass over samples [n_ch][n_in][row_stride] (bytes per
 // sample `sb`), n_samples per row, into the plan's accumulator.
-corr_status xengine_pass(corr_plan* p, const void* x, int sb, int64_t n_samples, int64_t row_stride) {
+corr_status xengine_pass(corr_plan* p, const void* x, int sb, int64_t n_samples, int64_t row_stride,
+                         int elem = -1, const float* inv_scale2 = nullptr) {
   const corr_config& c = p->cfg;
   const Layout& L = p->L;
   if (n_samples == 0) return CORR_OK;
@@ -164,12 +187,18 @@ corr_status xengine_pass(corr_plan* p, const void* x, int sb, int64_t n_samples,
   a.out = direct ? at(p, L.acc) : at(p, L.part);
   a.out_split_stride = direct ? 0 : (int64_t)c.n_channels * L.n_products;
   a.accumulate = direct ? (p->acc_zero ? 0 : 1) : 0;
+  a.inv_scale2 = inv_scale2;
   const bool aligned = (a.row_stride_b % 16 == 0) && ((reinterpret_cast<uintptr_t>(x) & 15) == 0);
 
   hipError_t e;
   const bool is_int = (c.engine == CORR_X_I8);
-  if (c.engine == CORR_X_I8) e = corr::launch_xeng_i8(a, L.bt, aligned, p->stream);
-  else e = corr::launch_xeng_f32(a, sb, L.bt, aligned, p->stream);
+  if (elem >= 0)
+    e = corr::launch_xeng_mfma(a, elem, L.bt, p->stream);  // staged FP16 / FP8 rows are aligned
+  else if (c.engine == CORR_X_I8)
+    e = aligned ? corr::launch_xeng_mfma(a, corr::kElemI8, L.bt, p->stream)
+                : corr::launch_xeng_i8(a, L.bt, false, p->stream);
+  else
+    e = corr::launch_xeng_f32(a, sb, L.bt, aligned, p->stream);
   if (e != hipSuccess) return hip_fail(p, e);
   if (!direct) {
     e = corr::launch_reduce_splits(at(p, L.part), (int64_t)c.n_channels * L.n_products, split, at(p, L.acc),
@@ -330,6 +359,32 @@ corr_status corr_correlate(corr_plan* p, const void* d_samples, int64_t n_sample
       if (c.engine == CORR_X_I8 && !within(c, total, 2147483647.0)) return CORR_E_OVERFLOW;
       if (c.engine == CORR_X_FP32 && !within(c, total, 16777216.0)) return CORR_E_OVERFLOW;
     }
+    if (c.engine == CORR_X_F16 || c.engine == CORR_X_F8) {
+      // Stage chunks of at most ring_samples samples, then correlate each.
+      const int elem = (c.engine == CORR_X_F16) ? corr::kElemF16 : corr::kElemF8;
+      for (int64_t t0 = 0; t0 < n; t0 += c.ring_samples) {
+        const int64_t nt = std::min<int64_t>(c.ring_samples, n - t0);
+        corr::LowpCall lc;
+        lc.x = static_cast<const float*>(x) + t0 * 2;
+        lc.n_ch = c.n_channels;
+        lc.n_in = c.n_inputs;
+        lc.n_t = nt;
+        lc.row_stride = stride;
+        lc.out_stride = p->L.stage_stride;
+        lc.elem = elem;
+        lc.out = at(p, p->L.stage);
+        lc.m_bits = static_cast<uint32_t*>(at(p, p->L.mbits));
+        lc.inv_scale2 = static_cast<float*>(at(p, p->L.scales));
+        const hipError_t e = corr::launch_lowp_stage(lc, p->stream);
+        if (e != hipSuccess) return hip_fail(p, e);
+        const corr_status st = xengine_pass(p, at(p, p->L.stage), p->L.stage_sb, nt, p->L.stage_stride, elem,
+                                            elem == corr::kElemF8 ? lc.inv_scale2 : nullptr);
+        if (st != CORR_OK) return st;
+        p->stage_fill = nt;
+      }
+      p->n_accum = total;
+      return CORR_OK;
+    }
     const corr_status s = xengine_pass(p, x, sb, n, stride);
     if (s != CORR_OK) return s;
     p->n_accum = total;
@@ -362,6 +417,54 @@ corr_status corr_ring_read(corr_plan* p, void* dst, int32_t dst_is_device, int64
   } catch (...) {
     return CORR_E_INVAL;
   }
+}
+
+corr_status corr_stage_read(corr_plan* p, void* dst, float* scales, int64_t* n_samples_out) {
+  try {
+    if (!p || !dst) return CORR_E_INVAL;
+    if (p->error) return CORR_E_STATE;
+    const corr_config& c = p->cfg;
+    if (c.engine != CORR_X_F16 && c.engine != CORR_X_F8) return CORR_E_STATE;
+    const int64_t n = p->stage_fill;
+    const int64_t rows = (int64_t)c.n_channels * c.n_inputs;
+    const int sb = p->L.stage_sb;
+    hipError_t e = hipSuccess;
+    if (n > 0) {
+      e = hipMemcpy2DAsync(dst, (size_t)n * sb, at(p, p->L.stage), (size_t)p->L.stage_stride * sb, (size_t)n * sb,
+                           (size_t)rows, hipMemcpyDeviceToHost, p->stream);
+      if (e != hipSuccess) return hip_fail(p, e);
+    }
+    std::vector<float> inv;
+    if (scales && c.engine == CORR_X_F8) {
+      inv.resize(c.n_channels);
+      e = hipMemcpyAsync(inv.data(), at(p, p->L.scales), inv.size() * sizeof(float), hipMemcpyDeviceToHost,
+                         p->stream);
+      if (e != hipSuccess) return hip_fail(p, e);
+    }
+    e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(p, e);
+    if (scales) {
+      for (int32_t k = 0; k < c.n_channels; ++k)
+        scales[k] = (c.engine == CORR_X_F8) ? (float)(1.0 / std::sqrt((double)inv[k])) : 1.0f;
+    }
+    if (n_samples_out) *n_samples_out = n;
+    return CORR_OK;
+  } catch (...) {
+    return CORR_E_INVAL;
+  }
+}
+
+corr_status corr_internal_dump_async(corr_plan* p, void* dst, int32_t dst_is_device, int64_t* n_samples_out) {
+  if (!p || !dst) return CORR_E_INVAL;
+  if (p->error) return CORR_E_STATE;
+  if (p->acc_zero) return CORR_E_STATE;  // nothing accumulated
+  const hipError_t e = hipMemcpyAsync(dst, at(p, p->L.acc), p->L.acc_bytes,
+                                      dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, p->stream);
+  if (e != hipSuccess) return hip_fail(p, e);
+  if (n_samples_out) *n_samples_out = p->n_accum;
+  p->acc_zero = true;
+  p->n_accum = 0;
+  return CORR_OK;
 }
 
 corr_status corr_dump_bytes(const corr_plan* p, int32_t what, size_t* bytes) {

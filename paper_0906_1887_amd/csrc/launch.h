@@ -11,6 +11,8 @@ struct FArgs;
 
 // int8 MFMA X-engine; bt = 64 or 128; aligned: rows and base 16-byte aligned.
 hipError_t launch_xeng_i8(const XArgs& a, int bt, bool aligned, hipStream_t s);
+// Matrix-core X-engine for 16-byte aligned rows; elem = kElemI8 / kElemF16 / kElemF8.
+hipError_t launch_xeng_mfma(const XArgs& a, int elem, int bt, hipStream_t s);
 // FP32 X-engine; sample_bytes = 8 (complex float32) or 2 (complex int8).
 hipError_t launch_xeng_f32(const XArgs& a, int sample_bytes, int bt, bool aligned, hipStream_t s);
 hipError_t launch_reduce_splits(const void* part, int64_t n_pairs, int n_split, void* acc, int accumulate,
@@ -31,5 +33,19 @@ struct FStageCall {
   float max_abs;
 };
 hipError_t launch_fstage_call(const FStageCall& c, hipStream_t s);
+
+struct LowpCall {
+  const float* x;          // complex float32 [n_ch][n_in][row_stride]
+  int64_t n_ch;
+  int64_t n_in;
+  int64_t n_t;             // samples converted per row
+  int64_t row_stride;      // input samples per row
+  int64_t out_stride;      // staged samples per row
+  int elem;                // kElemF16 or kElemF8
+  void* out;               // staged [n_ch][n_in][out_stride] (re, im) elements
+  uint32_t* m_bits;        // FP8: per-channel max |x| (float bits), scratch
+  float* inv_scale2;       // FP8: per-channel 1/s_c^2 (output)
+};
+hipError_t launch_lowp_stage(const LowpCall& c, hipStream_t s);
 
 }  // namespace corr

@@ -1,0 +1,322 @@
+// Matrix-core X-engine for aligned sample rows: int8 (int32 accumulation),
+// FP16 and OCP FP8 E4M3 (FP32 accumulation).
+//
+// V_ij[c] += sum_t x_i[c,t] conj(x_j[c,t]) -- the cross-multiply-accumulate
+// of Sec. 4 (third step), per channel, over the lower-triangle baseline tiles
+// of Fig. 2's outer product.  Each input row holds interleaved (re, im)
+// elements along K = 2T, so per channel
+//     Re V = A B^T            Im V = A (iB)^T,  iB = (-im_j, re_j)
+// and iB is formed from the staged B fragment in registers (a byte or
+// half-word rotation with a sign flip), so one LDS read feeds both products.
+//
+// Pipeline: a workgroup (4 waves, 2 x 2) owns a BT x BT tile of one channel.
+// Operand rows are staged 64 K-bytes at a time straight from global memory
+// into LDS (global_load_lds_dwordx4: no registers, no VALU), NS stages deep,
+// so loads for stage s+NS-1 are in flight while stage s feeds the MFMAs; one
+// barrier per stage.  LDS rows are 64 bytes with the four 16-byte chunks
+// XOR-permuted by row so that the 32 rows of an MFMA fragment read hit
+// distinct banks.  Rows past N_I are loaded from a clamped address and only
+// ever reach outputs that are never stored; bytes past the valid K range are
+// zeroed in LDS before use.  Tiles are numbered channel-major and remapped
+// from blockIdx.x so that each XCD (and its L2) runs a contiguous range of
+// channels.
+#include "common.h"
+#include "launch.h"
+
+namespace corr {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+constexpr int kMKC = 64;   // K bytes per stage
+constexpr int kMNS = 4;    // pipeline stages
+
+// 16-byte chunk c (0..3) of LDS row r lives at chunk c ^ swz(r).
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+// Multiply packed complex elements by i: (re, im) -> (-im, re).
+__device__ __forceinline__ int rot_i8(int w) {
+  const uint32_t u = (uint32_t)w;
+  const uint32_t im = (u >> 8) & 0x00FF00FFu;
+  const uint32_t neg = 0x01000100u - im;            // low byte of each 16-bit lane = -im
+  return (int)((neg & 0x00FF00FFu) | ((u << 8) & 0xFF00FF00u));
+}
+__device__ __forceinline__ int rot_f16(int w) {     // one complex half pair per dword
+  const uint32_t u = (uint32_t)w;
+  return (int)(((u >> 16) ^ 0x8000u) | (u << 16));
+}
+__device__ __forceinline__ int rot_f8(int w) {      // two complex fp8 pairs per dword
+  const uint32_t u = (uint32_t)w;
+  const uint32_t sw = ((u >> 8) & 0x00FF00FFu) | ((u << 8) & 0xFF00FF00u);
+  return (int)(sw ^ 0x00800080u);
+}
+
+template <int EK>
+__device__ __forceinline__ v4i rot4(v4i v) {
+  v4i r;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    r[q] = EK == kElemI8 ? rot_i8(v[q]) : (EK == kElemF16 ? rot_f16(v[q]) : rot_f8(v[q]));
+  return r;
+}
+
+template <int EK>
+struct MAcc;
+template <>
+struct MAcc<kElemI8> { typedef v16i T; };
+template <>
+struct MAcc<kElemF16> { typedef v16f T; };
+template <>
+struct MAcc<kElemF8> { typedef v16f T; };
+
+// One 64-byte K stage of a 32 x 32 block: fragments are two 16-byte reads per
+// lane (K bytes g*16.. and 32+g*16.., g = lane / 32) of A and of B.
+template <int EK>
+__device__ __forceinline__ void mfma64(const v4i (&a)[2], const v4i (&b)[2], typename MAcc<EK>::T& acc) {
+  if constexpr (EK == kElemI8) {
+    acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[0], b[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[1], b[1], acc, 0, 0, 0);
+  } else if constexpr (EK == kElemF16) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a[0]), __builtin_bit_cast(v8h, b[0]),
+                                                  acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a[1]), __builtin_bit_cast(v8h, b[1]),
+                                                  acc, 0, 0, 0);
+  } else {
+    const v8i a8 = {a[0][0], a[0][1], a[0][2], a[0][3], a[1][0], a[1][1], a[1][2], a[1][3]};
+    const v8i b8 = {b[0][0], b[0][1], b[0][2], b[0][3], b[1][0], b[1][1], b[1][2], b[1][3]};
+    // format 0 (FP8 E4M3) for both operands, unit E8M0 scales (127 = 2^0)
+    acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, acc, 0, 0, 0, 127, 0, 127);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+template <int EK, int BT, bool DIAG>
+__device__ __forceinline__ void mfma_tile(const XArgs& a, int8_t* lds, int ch, int split, int I, int J) {
+  constexpr int WT = BT / 2;                 // wave tile
+  constexpr int MB = WT / 32;                // 32 x 32 blocks per wave side
+  constexpr int PANEL = BT * kMKC;           // bytes per operand per stage
+  constexpr int STAGE = PANEL * (DIAG ? 1 : 2);
+  constexpr int QPW = BT / 16 / 4;           // 1 KB load instructions per operand per wave
+  constexpr int LPW = QPW * (DIAG ? 1 : 2);  // load instructions per wave per stage
+  using Acc = typename MAcc<EK>::T;
+
+  const int8_t* __restrict__ xc = static_cast<const int8_t*>(a.x) + (int64_t)ch * a.ch_stride_b;
+  const int64_t k0 = (int64_t)split * a.k_split_bytes;
+  const int64_t k1 = min(a.k_bytes, k0 + a.k_split_bytes);
+  const int n_st = k1 > k0 ? (int)((k1 - k0 + kMKC - 1) / kMKC) : 0;
+  const int64_t last = ((k1 - 1) >> 4) << 4;  // last valid 16-byte chunk start
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const bool wave_idle = DIAG && (wm < wn);
+
+  // This lane's part of each load instruction: LDS row lrow (of 16), chunk p.
+  const int lrow = lane >> 2, p = lane & 3;
+  const int8_t* gA[QPW];
+  const int8_t* gB[QPW];
+  int rowq[QPW];
+#pragma unroll
+  for (int q = 0; q < QPW; ++q) {
+    const int r = (wave * QPW + q) * 16 + lrow;    // tile row
+    rowq[q] = r;
+    const int c = p ^ swz(r);                      // global chunk this lane fetches
+    const int ra = min(I * BT + r, a.n_in - 1);
+    gA[q] = xc + (int64_t)ra * a.row_stride_b + 16 * c;
+    if (!DIAG) {
+      const int rb = min(J * BT + r, a.n_in - 1);
+      gB[q] = xc + (int64_t)rb * a.row_stride_b + 16 * c;
+    }
+  }
+
+  auto issue = [&](int st) {
+    int8_t* base = lds + (st % kMNS) * STAGE;
+    const int64_t kb = k0 + (int64_t)st * kMKC;
+#pragma unroll
+    for (int q = 0; q < QPW; ++q) {
+      const int c = p ^ swz(rowq[q]);
+      const int64_t kk = kb + 16 * c;
+      const int64_t off = (kk <= last ? kb : last - 16 * c);   // keep the 16 bytes inside the row
+      int8_t* dst = base + (wave * QPW + q) * 1024;
+      __builtin_amdgcn_global_load_lds(gA[q] + off, dst, 16, 0, 0);
+      if (!DIAG) __builtin_amdgcn_global_load_lds(gB[q] + off, dst + PANEL, 16, 0, 0);
+    }
+  };
+  // Zero / mask the chunks of stage st that reach past k1 (only the last stage).
+  auto fix_tail = [&](int st) {
+    int8_t* base = lds + (st % kMNS) * STAGE;
+    const int64_t kb = k0 + (int64_t)st * kMKC;
+#pragma unroll
+    for (int q = 0; q < QPW; ++q) {
+      const int c = p ^ swz(rowq[q]);
+      const int64_t kk = kb + 16 * c;
+      if (kk + 16 > k1) {
+        const int64_t valid = k1 - kk;
+#pragma unroll
+        for (int op = 0; op < (DIAG ? 1 : 2); ++op) {
+          v4i* cell = reinterpret_cast<v4i*>(base + op * PANEL + (wave * QPW + q) * 1024 + lane * 16);
+          v4i v = *cell;
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            const int64_t lo = 4 * w;
+            const int keep = valid >= lo + 4 ? 4 : (valid > lo ? (int)(valid - lo) : 0);
+            const uint32_t m = keep >= 4 ? 0xFFFFFFFFu : ((1u << (8 * keep)) - 1u);
+            v[w] = (int)((uint32_t)v[w] & m);
+          }
+          *cell = v;
+        }
+      }
+    }
+  };
+
+  Acc vr[MB][MB], vi[MB][MB];
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int n = 0; n < MB; ++n)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        vr[m][n][r] = 0;
+        vi[m][n][r] = 0;
+      }
+
+#pragma unroll
+  for (int s = 0; s < kMNS - 1; ++s)
+    if (s < n_st) issue(s);
+
+  const int frow = lane & 31;
+  const int g = lane >> 5;
+  const bool tail = (k1 - k0) % kMKC != 0;
+  for (int s = 0; s < n_st; ++s) {
+    // Wait for this wave's loads of stage s; later stages may stay in flight.
+    const int ahead = min(kMNS - 2, n_st - 1 - s);
+    if (ahead >= 2) wait_vmcnt<2 * LPW>();
+    else if (ahead == 1) wait_vmcnt<LPW>();
+    else wait_vmcnt<0>();
+    if (tail && s == n_st - 1) {
+      fix_tail(s);
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    }
+    // Plain s_barrier (as asm with a memory clobber, so the compiler keeps
+    // LDS reads below it): each wave has already waited for its own stage-s
+    // loads, which is all the other waves need; a fenced barrier would also
+    // drain the loads of later stages that are meant to stay in flight.
+    asm volatile("s_barrier" ::: "memory");
+    if (s + kMNS - 1 < n_st) issue(s + kMNS - 1);
+    if (!wave_idle) {
+      const int8_t* As = lds + (s % kMNS) * STAGE;
+      const int8_t* Bs = DIAG ? As : As + PANEL;
+      v4i af[MB][2], bf[MB][2], bj[MB][2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int cidx = 2 * h + g;            // logical 16-byte chunk
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+          const int r = wm * WT + m * 32 + frow;
+          af[m][h] = *reinterpret_cast<const v4i*>(As + r * kMKC + 16 * (cidx ^ swz(r)));
+        }
+#pragma unroll
+        for (int n = 0; n < MB; ++n) {
+          const int r = wn * WT + n * 32 + frow;
+          bf[n][h] = *reinterpret_cast<const v4i*>(Bs + r * kMKC + 16 * (cidx ^ swz(r)));
+          bj[n][h] = rot4<EK>(bf[n][h]);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int n = 0; n < MB; ++n) {
+          if (DIAG && wm == wn && m < n) continue;   // strictly upper 32 x 32 block
+          mfma64<EK>(af[m], bf[n], vr[m][n]);
+          mfma64<EK>(af[m], bj[n], vi[m][n]);
+        }
+    }
+  }
+
+  if (wave_idle) return;
+  // Epilogue.  32 x 32 accumulator layout: register r of lane l holds row
+  // 8*(r/4) + 4*(l/32) + r%4, column l%32.
+  float scale = 1.0f;
+  if constexpr (EK == kElemF8) scale = a.inv_scale2 ? a.inv_scale2[ch] : 1.0f;
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int n = 0; n < MB; ++n) {
+      if (DIAG && wm == wn && m < n) continue;
+      const int j = J * BT + wn * WT + n * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = I * BT + wm * WT + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (i < a.n_in && j <= i) {
+          const int64_t off = (int64_t)split * a.out_split_stride + (int64_t)ch * a.n_products + tri_index(i, j);
+          if constexpr (EK == kElemI8) {
+            int2* pp = static_cast<int2*>(a.out) + off;
+            const int re = vr[m][n][r];
+            const int im = (i == j) ? 0 : vi[m][n][r];
+            if (a.accumulate) {
+              int2 o = *pp;
+              o.x += re;
+              o.y += im;
+              *pp = o;
+            } else {
+              *pp = make_int2(re, im);
+            }
+          } else {
+            float2* pp = static_cast<float2*>(a.out) + off;
+            const float re = vr[m][n][r] * scale;
+            const float im = (i == j) ? 0.f : vi[m][n][r] * scale;
+            if (a.accumulate) {
+              float2 o = *pp;
+              o.x += re;
+              o.y += im;
+              *pp = o;
+            } else {
+              *pp = make_float2(re, im);
+            }
+          }
+        }
+      }
+    }
+}
+
+template <int EK, int BT>
+__global__ __launch_bounds__(256, 2) void xeng_mfma_kernel(XArgs a) {
+  __shared__ __attribute__((aligned(1024))) int8_t lds[kMNS * 2 * BT * kMKC];
+  const int64_t slot = blockIdx.x / kNumXcd;
+  const int64_t item = xcd_item(blockIdx.x, a.per_xcd);
+  if (slot >= a.per_xcd || item >= a.n_items) return;
+  const int tile = (int)(item % a.n_tiles);
+  const int64_t rest = item / a.n_tiles;
+  const int split = (int)(rest % a.n_split);
+  const int ch = (int)(rest / a.n_split);
+  int I, J;
+  tile_decode(tile, I, J);
+  if (I == J) mfma_tile<EK, BT, true>(a, lds, ch, split, I, J);
+  else mfma_tile<EK, BT, false>(a, lds, ch, split, I, J);
+}
+
+hipError_t launch_xeng_mfma(const XArgs& a, int elem, int bt, hipStream_t s) {
+  const int64_t grid = (int64_t)a.per_xcd * kNumXcd;
+  if (grid <= 0) return hipSuccess;
+  const dim3 g((unsigned)grid), b(256);
+#define CORR_LAUNCH(EK, BT) hipLaunchKernelGGL((xeng_mfma_kernel<EK, BT>), g, b, 0, s, a)
+  if (elem == kElemI8) {
+    if (bt == 128) CORR_LAUNCH(kElemI8, 128); else CORR_LAUNCH(kElemI8, 64);
+  } else if (elem == kElemF16) {
+    if (bt == 128) CORR_LAUNCH(kElemF16, 128); else CORR_LAUNCH(kElemF16, 64);
+  } else {
+    if (bt == 128) CORR_LAUNCH(kElemF8, 128); else CORR_LAUNCH(kElemF8, 64);
+  }
+#undef CORR_LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace corr

@@ -227,6 +227,9 @@ def real_voltages(seed: int, index: int, n_blocks: int, n_inputs: int = 64,
 # Complex Gaussian float inputs with per-input gains and coherent pairs.
 # ---------------------------------------------------------------------------
 def coherent_pairs(seed: int, n_inputs: int, n_pairs: int = 16):
+    """n_pairs disjoint input pairs from a seeded permutation (fewer when
+    n_inputs < 2 n_pairs)."""
+    n_pairs = min(n_pairs, n_inputs // 2)
     rng = np.random.default_rng([seed, 0x9A15])
     perm = rng.permutation(n_inputs)[: 2 * n_pairs]
     return [(int(perm[2 * k]), int(perm[2 * k + 1])) for k in range(n_pairs)]
@@ -240,22 +243,23 @@ def input_gains(seed: int, n_inputs: int, lo: float = 0.5, hi: float = 2.0) -> n
 def complex_float(seed: int, ch: int, n_inputs: int, n_samples: int,
                   rho: float = 0.1, n_pairs: int = 16) -> np.ndarray:
     """One channel, float32 [n_inputs][n_samples][2]: x = g*(sqrt(1-rho) n + sqrt(rho) c)
-    on each coherent pair (c common to the pair), x = g*n elsewhere; n, c ~ CN(0,1)."""
-    g = input_gains(seed, n_inputs)
+    on each coherent pair (c common to the pair), x = g*n elsewhere; n, c ~ CN(0,1)
+    (independent N(0, 1/2) real and imaginary parts)."""
+    g = input_gains(seed, n_inputs).astype(np.float32)
     pairs = coherent_pairs(seed, n_inputs, n_pairs)
     rng = np.random.default_rng([seed, 1, ch])
-    s = math.sqrt(0.5)
-    n = s * (rng.standard_normal((n_inputs, n_samples)) + 1j * rng.standard_normal((n_inputs, n_samples)))
-    c = s * (rng.standard_normal((n_pairs, n_samples)) + 1j * rng.standard_normal((n_pairs, n_samples)))
-    x = n.copy()
-    for p, (i, j) in enumerate(pairs):
-        x[i] = math.sqrt(1 - rho) * n[i] + math.sqrt(rho) * c[p]
-        x[j] = math.sqrt(1 - rho) * n[j] + math.sqrt(rho) * c[p]
-    x *= g[:, None]
-    out = np.empty((n_inputs, n_samples, 2), dtype=np.float32)
-    out[..., 0] = x.real
-    out[..., 1] = x.imag
-    return out
+    s = np.float32(math.sqrt(0.5))
+    x = rng.standard_normal((n_inputs, n_samples, 2), dtype=np.float32)
+    x *= s
+    c = rng.standard_normal((len(pairs), n_samples, 2), dtype=np.float32)
+    c *= s
+    a = np.float32(math.sqrt(1.0 - rho))
+    b = np.float32(math.sqrt(rho))
+    for k, (i, j) in enumerate(pairs):
+        x[i] = a * x[i] + b * c[k]
+        x[j] = a * x[j] + b * c[k]
+    x *= g[:, None, None]
+    return x
 
 
 # ---------------------------------------------------------------------------
@@ -284,6 +288,10 @@ class _Thr(ctypes.Structure):
     _fields_ = [("t", ctypes.c_uint32 * 16), ("n", ctypes.c_int32), ("max_abs", ctypes.c_int32)]
 
 
+class _JobFill(ctypes.Structure):
+    _fields_ = [("base_seed", ctypes.c_uint64), ("th", _Thr)]
+
+
 class DeviceGen:
     """ctypes wrapper of ``synth_fill_ci8`` (``libsynth.so``)."""
 
@@ -295,6 +303,19 @@ class DeviceGen:
             ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
             ctypes.c_int64, ctypes.c_uint64, ctypes.POINTER(_Thr), ctypes.c_void_p]
         self.lib.synth_fill_ci8.restype = ctypes.c_int
+
+    def job_fill(self, base_seed: int, sigma: float = 2.0, max_abs: int = 7):
+        """(function pointer, user pointer, keep-alive) for a serving-scheduler
+        fill callback: job j gets the ci8 signal of seed base_seed + j."""
+        thr = level_thresholds(sigma, max_abs)
+        jf = _JobFill()
+        jf.base_seed = base_seed
+        for i, v in enumerate(thr):
+            jf.th.t[i] = int(v)
+        jf.th.n = thr.size
+        jf.th.max_abs = max_abs
+        fn = ctypes.cast(self.lib.synth_fill_job, ctypes.c_void_p).value
+        return fn, ctypes.addressof(jf), jf
 
     def fill_ci8(self, d_ptr: int, n_channels: int, n_inputs: int, n_samples: int,
                  seed: int, sigma: float = 2.0, max_abs: int = 7, stream: int = 0,

@@ -89,3 +89,19 @@ extern "C" int synth_fill_ci8(void* d_out, int64_t ch0, int64_t n_ch, int64_t n_
                      (int8_t*)d_out, ch0, n_in, n_t, row_stride, rows, host_mix64(seed), *th);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
+
+namespace {
+struct JobFill {
+  uint64_t base_seed;
+  Thresholds th;
+};
+}  // namespace
+
+// Fill callback for the serving scheduler: job `job_id` gets the ci8 signal
+// of seed base_seed + job_id (user points to a JobFill).  Queues one kernel on
+// `stream`; never blocks.
+extern "C" void synth_fill_job(void* user, uint64_t job_id, void* d_samples, int64_t n_ch, int64_t n_in,
+                               int64_t n_t, void* stream) {
+  const JobFill* f = static_cast<const JobFill*>(user);
+  synth_fill_ci8(d_samples, 0, n_ch, n_in, n_t, n_t, f->base_seed + job_id, &f->th, stream);
+}

@@ -36,6 +36,9 @@ def test_workspace_and_validation():
     from paper_0906_1887_amd import _lib
     ws = _lib.corr_workspace_bytes(_cfg(n_inputs=1024, n_channels=768, engine="i8"))
     assert ws >= 768 * 524800 * 8
+    lowp = _lib.corr_workspace_bytes(_cfg(n_inputs=256, n_channels=1024, engine="f8", sample_type="cf32",
+                                          max_abs=0, ring_samples=4096))
+    assert lowp >= 1024 * 32896 * 8 + 1024 * 256 * 4096 * 2
     small = _lib.corr_workspace_bytes(_cfg(n_inputs=64, n_channels=128, engine="i8"))
     assert small > 128 * 2080 * 8        # includes K-split partials at small N_I
     fx = _lib.corr_workspace_bytes(_cfg(n_inputs=64, n_channels=128, engine="i8", fft_size=256,
@@ -49,13 +52,15 @@ def test_workspace_and_validation():
         dict(n_inputs=4, n_channels=64, fft_size=256, requant_scale=0.1, ring_samples=10),
         dict(n_inputs=4, n_channels=128, fft_size=256, requant_scale=0.0, ring_samples=10),
         dict(n_inputs=4, n_channels=128, fft_size=256, requant_scale=0.1, ring_samples=0),
+        dict(n_inputs=4, n_channels=4, engine="f16", sample_type="ci8", max_abs=0, ring_samples=64),
+        dict(n_inputs=4, n_channels=4, engine="f8", sample_type="cf32", max_abs=7, ring_samples=64),
+        dict(n_inputs=4, n_channels=4, engine="f8", sample_type="cf32", max_abs=0, ring_samples=0),
     ]
     for kw in bad:
         with pytest.raises(_lib.CorrError) as e:
             _lib.corr_workspace_bytes(_cfg(**kw))
         assert e.value.status == _lib.CORR_E_INVAL, kw
-    for kw in (dict(n_inputs=4, n_channels=64, fft_size=128, requant_scale=0.1, ring_samples=10),
-               dict(n_inputs=4, n_channels=4, engine="f16", sample_type="cf32", max_abs=0)):
+    for kw in (dict(n_inputs=4, n_channels=64, fft_size=128, requant_scale=0.1, ring_samples=10),):
         with pytest.raises(_lib.CorrError) as e:
             _lib.corr_workspace_bytes(_cfg(**kw))
         assert e.value.status == _lib.CORR_E_UNSUPPORTED, kw

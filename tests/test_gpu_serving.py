@@ -1,0 +1,122 @@
+"""Serving scheduler on the GPU through the C ABI: each job's result is the
+same alone and inside a concurrent mix (bit-exact, integer data), matches the
+oracle, and admission by HBM footprint queues jobs that do not fit."""
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_0906_1887_amd import CorrError, Scheduler, _lib
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+BASE_SEED = 5000
+
+JOBS = [(16, 64, 1000), (512, 64, 1500), (64, 256, 2000), (128, 64, 1234), (1024, 64, 1000),
+        (16, 256, 3000), (64, 64, 999), (512, 256, 1200), (128, 256, 1001), (16, 64, 8000),
+        (1024, 64, 2048), (64, 768, 1000)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def result_buf(n_in, n_ch, device=True):
+    P = n_in * (n_in + 1) // 2
+    return torch.empty((n_ch, P, 2), dtype=torch.int32, device=DEV if device else "cpu")
+
+
+def wait(s, jid, timeout=60.0):
+    t0 = time.time()
+    while True:
+        r = s.poll(jid)
+        if r is not None:
+            return r
+        assert time.time() - t0 < timeout, f"job {jid} not done"
+        time.sleep(0.0005)
+
+
+def run_jobs(jobs, concurrent, arena_bytes=8 << 30, n_streams=4):
+    gen = synth.DeviceGen()
+    fn, user, keep = gen.job_fill(BASE_SEED)
+    s = Scheduler(arena_bytes, n_streams)
+    outs, ids, lat = [], [], []
+    try:
+        for (n_in, n_ch, T) in jobs:
+            out = result_buf(n_in, n_ch)
+            jid = s.submit(n_in, n_ch, T, out, fill=fn, fill_user=user)
+            outs.append(out)
+            ids.append(jid)
+            if not concurrent:
+                st, n, ta, td = wait(s, jid)
+                assert st == 0 and n == T
+        if concurrent:
+            for jid, (n_in, n_ch, T) in zip(ids, jobs):
+                st, n, ta, td = wait(s, jid)
+                assert st == 0 and n == T
+        stats = s.stats()
+    finally:
+        s.close()
+    del keep
+    return ids, [o.cpu().numpy() for o in outs], stats
+
+
+def test_alone_equals_mix_and_oracle():
+    say("[serving] alone")
+    ids_a, alone, _ = run_jobs(JOBS, concurrent=False)
+    say("[serving] mix")
+    ids_m, mix, stats = run_jobs(JOBS, concurrent=True)
+    assert ids_a == ids_m == list(range(1, len(JOBS) + 1))
+    assert stats["completed"] == len(JOBS) and stats["failed"] == 0
+    for k, (a, m) in enumerate(zip(alone, mix)):
+        assert np.array_equal(a, m), f"job {k} differs alone vs mix"
+    # oracle on the smaller jobs (host regeneration of seed BASE_SEED + job id)
+    for k, (n_in, n_ch, T) in enumerate(JOBS):
+        if n_in * n_in * n_ch * T > 3e10:
+            continue
+        x = synth.ci8(BASE_SEED + ids_a[k], n_ch, n_in, T)
+        assert np.array_equal(mix[k].astype(np.int64), oracle.xengine_ci8(x)), k
+
+
+def test_admission_queues_when_arena_is_small():
+    jobs = [(128, 64, 2000)] * 6 + [(16, 64, 1000)] * 4
+    from paper_0906_1887_amd import make_config
+    ws = _lib.corr_workspace_bytes(make_config(128, 64, engine="i8", max_abs=7))
+    foot = 64 * 128 * 2000 * 2 + ws
+    arena = int(2.5 * foot) // 256 * 256          # at most two of the large jobs at once
+    say(f"[serving] small arena {arena / 2**20:.1f} MiB, job footprint {foot / 2**20:.1f} MiB")
+    ids, outs, stats = run_jobs(jobs, concurrent=True, arena_bytes=arena, n_streams=4)
+    assert stats["completed"] == len(jobs)
+    assert stats["peak_arena_bytes"] <= stats["arena_bytes"]
+    first = outs[0]
+    x = synth.ci8(BASE_SEED + ids[0], 64, 128, 2000)
+    assert np.array_equal(first.astype(np.int64), oracle.xengine_ci8(x))
+    fn, user, keep = synth.DeviceGen().job_fill(BASE_SEED)
+    s = Scheduler(64 << 20, 2)
+    try:
+        with pytest.raises(CorrError) as e:               # footprint beyond the whole arena
+            s.submit(1024, 768, 8000, result_buf(1, 1), fill=fn, fill_user=user)
+        assert e.value.status == _lib.CORR_E_WORKSPACE
+    finally:
+        s.close()
+    del keep
+
+
+def test_caller_device_samples_and_host_result():
+    n_in, n_ch, T = 40, 3, 333
+    x = synth.ci8(77, n_ch, n_in, T)
+    xt = torch.from_numpy(x).to(DEV)
+    out = result_buf(n_in, n_ch, device=False).pin_memory()
+    s = Scheduler(64 << 20, 2)
+    try:
+        jid = s.submit(n_in, n_ch, T, out, d_samples=xt.data_ptr())
+        st, n, ta, td = wait(s, jid)
+        assert st == 0 and n == T and td >= ta
+    finally:
+        s.close()
+    assert np.array_equal(out.numpy().astype(np.int64), oracle.xengine_ci8(x))
