@@ -53,6 +53,88 @@ def cpu_baseline(x_dev, n_channels: int) -> dict:
             "seconds": dt, "host_threads": threads, "nproc": os.cpu_count()}
 
 
+def serving(seconds: float, warm: float, rate: float, seed: int = 5) -> dict:
+    """Poisson arrivals (rate jobs/s) of integration jobs with N_I in {16, 64,
+    128, 512, 1024}, N_C in {64, 256, 768}, T uniform in 1000..8000, samples
+    produced on the device by the seeded generator (seed 5000 + job id) when a
+    job is admitted, results landing in device buffers.  Latency = result
+    landed - scheduled arrival.  Jobs arriving in the first `warm` seconds are
+    excluded from the statistics."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_0906_1887_amd import Scheduler, corr_sched_now
+
+    rng = np.random.default_rng(seed)
+    n_jobs = int(seconds * rate * 1.2) + 10
+    gaps = rng.exponential(1.0 / rate, n_jobs)
+    t_rel = np.cumsum(gaps)
+    t_rel = t_rel[t_rel < seconds]
+    shapes = [(int(rng.choice([16, 64, 128, 512, 1024])), int(rng.choice([64, 256, 768])),
+               int(rng.integers(1000, 8001))) for _ in range(t_rel.size)]
+    max_res = 768 * 524800 * 8
+    n_slots = 16
+    slots = [torch.empty(max_res // 4, dtype=torch.int32, device="cuda:0") for _ in range(n_slots)]
+    free = list(range(n_slots))
+    gen = synth.DeviceGen()
+    fn, user, keep = gen.job_fill(5000)
+    sched = Scheduler(64 << 30, n_streams=4)
+    # one small job to initialise everything before the clock starts
+    j0 = sched.submit(16, 64, 1000, slots[0], fill=fn, fill_user=user)
+    while sched.poll(j0) is None:
+        time.sleep(0.001)
+    inflight = {}          # job id -> (k, slot)
+    done = []              # (k, t_arrival, t_admit, t_done)
+    t0 = corr_sched_now() + 0.05
+    k = 0
+    while k < len(shapes) or inflight:
+        now = corr_sched_now()
+        for jid in list(inflight):
+            r = sched.poll(jid)
+            if r is not None:
+                kk, slot = inflight.pop(jid)
+                st, n, ta, td = r
+                if st != 0:
+                    raise RuntimeError(f"serving job {kk} failed with status {st}")
+                done.append((kk, t0 + t_rel[kk], ta, td))
+                free.append(slot)
+        while k < len(shapes) and t0 + t_rel[k] <= now and free:
+            n_in, n_ch, T = shapes[k]
+            slot = free.pop()
+            jid = sched.submit(n_in, n_ch, T, slots[slot], fill=fn, fill_user=user, t_arrival=t0 + t_rel[k])
+            inflight[jid] = (k, slot)
+            k += 1
+        time.sleep(0.0002)
+    stats = sched.stats()
+    sched.close()
+    del keep
+    done.sort()
+    lat, wait, tint1, tint2, cm = [], [], [], [], 0
+    for kk, ta_sched, ta, td in done:
+        if t_rel[kk] < warm:
+            continue
+        n_in, n_ch, T = shapes[kk]
+        lat.append(td - ta_sched)
+        wait.append(ta - ta_sched)
+        tint1.append(T / 10e3)                 # 10 kHz channels (1.28 MHz / 128)
+        tint2.append(T * n_ch / 1.28e6)        # the 1.28 MHz band split into N_C channels
+        cm += n_ch * n_in * (n_in + 1) // 2 * T
+    lat = np.array(lat)
+    span = max(td for _, _, _, td in done) - (t0 + warm)
+    return {"jobs": int(lat.size), "offered_rate_per_s": rate, "seconds": seconds, "warmup_s": warm,
+            "throughput_jobs_per_s": lat.size / span, "throughput_tcmac_s": cm / span / 1e12,
+            "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
+                           "max": float(lat.max() * 1e3), "mean": float(lat.mean() * 1e3)},
+            "admission_wait_ms_p99": float(np.percentile(wait, 99) * 1e3),
+            "frac_within_own_integration_time": {
+                "T_over_10kHz": float(np.mean(lat < np.array(tint1))),
+                "T_times_NC_over_1.28MHz": float(np.mean(lat < np.array(tint2)))},
+            "p99_below_50ms": bool(np.percentile(lat, 99) < 0.050),
+            "scheduler": stats, "streams": 4, "arena_GiB": 64,
+            "latency_end": "integration landed in the job's device result buffer"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +143,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-channels", type=int, default=16)
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
                     help="copy: only a 1 GiB device-to-device copy, the known-size reference for "
                          "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -161,9 +245,22 @@ def main() -> int:
             "traffic": None, "kernel": "xeng_i8_kernel<128,true>", "kernel_ms_avg": kern_avg,
             "kernel_ms_min": kern_ms[0], "kernel_ms_median": kern_ms[len(kern_ms) // 2]}
 
+    serve = None
+    if not args.no_serving:
+        log("serving loop")
+        del x
+        torch.cuda.empty_cache()
+        serve = serving(args.serve_seconds, warm=1.0, rate=200.0)
+        x = None
+
     cpu = None
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
+        if x is None:
+            x = torch.empty((args.cpu_channels, N_IN, N_T, 2), dtype=torch.int8, device=dev)
+            synth.DeviceGen().fill_ci8(x.data_ptr(), args.cpu_channels, N_IN, N_T, SEED,
+                                       stream=stream.cuda_stream)
+            torch.cuda.synchronize()
         cpu = cpu_baseline(x, args.cpu_channels)
 
     value = cmac / (ms_per_step / 1e3) / 1e12
@@ -186,6 +283,7 @@ def main() -> int:
         "roofline": roof,
         "cpu_baseline": cpu,
         "fp32_plain": fp32,
+        "serving": serve,
         "dump_ms": {"device": dump_dev_ms, "host_pinned": dump_host_ms, "bytes": N_CH * N_IN * (N_IN + 1) // 2 * 8},
         "paper_context": "60x over one CPU thread at 32 antennas on 2008 NVIDIA hardware (abstract); context only",
     }

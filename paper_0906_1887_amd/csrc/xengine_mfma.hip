@@ -287,6 +287,248 @@ __device__ __forceinline__ void mfma_tile(const XArgs& a, int8_t* lds, int ch, i
     }
 }
 
+// Multiply packed complex elements by -i: (re, im) -> (im, -re).
+__device__ __forceinline__ int rotm_i8(int w) {
+  const uint32_t u = (uint32_t)w;
+  const uint32_t neg = 0x01000100u - (u & 0x00FF00FFu);   // low byte of each 16-bit lane = -re
+  // bytes: im0 (u.1), -re0 (neg.0), im1 (u.3), -re1 (neg.2)
+  return (int)__builtin_amdgcn_perm(neg, u, 0x06030401u);
+}
+__device__ __forceinline__ int rotm_f16(int w) {
+  const uint32_t u = (uint32_t)w;
+  return (int)(((u >> 16) | (u << 16)) ^ 0x80000000u);
+}
+__device__ __forceinline__ int rotm_f8(int w) {
+  const uint32_t u = (uint32_t)w;
+  const uint32_t sw = ((u >> 8) & 0x00FF00FFu) | ((u << 8) & 0xFF00FF00u);
+  return (int)(sw ^ 0x80008000u);
+}
+
+template <int EK>
+__device__ __forceinline__ v4i rotm4(v4i v) {
+  v4i r;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    r[q] = EK == kElemI8 ? rotm_i8(v[q]) : (EK == kElemF16 ? rotm_f16(v[q]) : rotm_f8(v[q]));
+  return r;
+}
+
+// 128 x 128 tile with two waves, each owning 64 rows x 128 columns (2 x 4
+// blocks of 32 x 32, Re and Im: 256 accumulator registers per lane).  Against
+// four waves of 64 x 64 this cuts LDS reads per MFMA by a quarter, and the
+// -i rotation moves to the A fragments (2 blocks instead of 4 per wave):
+// Im V = (-iA) B^T with -iA = (im_i, -re_i).
+template <int EK, bool DIAG>
+__device__ __forceinline__ void mfma_tile_w2(const XArgs& a, int8_t* lds, int ch, int split, int I, int J) {
+  constexpr int BT = 128;
+  constexpr int PANEL = BT * kMKC;           // bytes per operand per stage
+  constexpr int STAGE = PANEL * (DIAG ? 1 : 2);
+  constexpr int QPW = BT / 16 / 2;           // 1 KB load instructions per operand per wave
+  constexpr int LPW = QPW * (DIAG ? 1 : 2);  // load instructions per wave per stage
+  using Acc = typename MAcc<EK>::T;
+
+  const int8_t* __restrict__ xc = static_cast<const int8_t*>(a.x) + (int64_t)ch * a.ch_stride_b;
+  const int64_t k0 = (int64_t)split * a.k_split_bytes;
+  const int64_t k1 = min(a.k_bytes, k0 + a.k_split_bytes);
+  const int n_st = k1 > k0 ? (int)((k1 - k0 + kMKC - 1) / kMKC) : 0;
+  const int64_t last = ((k1 - 1) >> 4) << 4;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;                 // 0, 1: rows wave*64 .. +63
+
+  const int lrow = lane >> 2, p = lane & 3;
+  const int8_t* gA[QPW];
+  const int8_t* gB[QPW];
+  int rowq[QPW];
+#pragma unroll
+  for (int q = 0; q < QPW; ++q) {
+    const int r = (wave * QPW + q) * 16 + lrow;
+    rowq[q] = r;
+    const int c = p ^ swz(r);
+    gA[q] = xc + (int64_t)min(I * BT + r, a.n_in - 1) * a.row_stride_b + 16 * c;
+    if (!DIAG) gB[q] = xc + (int64_t)min(J * BT + r, a.n_in - 1) * a.row_stride_b + 16 * c;
+  }
+  auto issue = [&](int st) {
+    int8_t* base = lds + (st % kMNS) * STAGE;
+    const int64_t kb = k0 + (int64_t)st * kMKC;
+#pragma unroll
+    for (int q = 0; q < QPW; ++q) {
+      const int c = p ^ swz(rowq[q]);
+      const int64_t kk = kb + 16 * c;
+      const int64_t off = (kk <= last ? kb : last - 16 * c);
+      int8_t* dst = base + (wave * QPW + q) * 1024;
+      __builtin_amdgcn_global_load_lds(gA[q] + off, dst, 16, 0, 0);
+      if (!DIAG) __builtin_amdgcn_global_load_lds(gB[q] + off, dst + PANEL, 16, 0, 0);
+    }
+  };
+  auto fix_tail = [&](int st) {
+    int8_t* base = lds + (st % kMNS) * STAGE;
+    const int64_t kb = k0 + (int64_t)st * kMKC;
+#pragma unroll
+    for (int q = 0; q < QPW; ++q) {
+      const int c = p ^ swz(rowq[q]);
+      const int64_t kk = kb + 16 * c;
+      if (kk + 16 > k1) {
+        const int64_t valid = k1 - kk;
+#pragma unroll
+        for (int op = 0; op < (DIAG ? 1 : 2); ++op) {
+          v4i* cell = reinterpret_cast<v4i*>(base + op * PANEL + (wave * QPW + q) * 1024 + lane * 16);
+          v4i v = *cell;
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            const int64_t lo = 4 * w;
+            const int keep = valid >= lo + 4 ? 4 : (valid > lo ? (int)(valid - lo) : 0);
+            const uint32_t m = keep >= 4 ? 0xFFFFFFFFu : ((1u << (8 * keep)) - 1u);
+            v[w] = (int)((uint32_t)v[w] & m);
+          }
+          *cell = v;
+        }
+      }
+    }
+  };
+
+  Acc vr[2][4], vi[2][4];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        vr[m][n][r] = 0;
+        vi[m][n][r] = 0;
+      }
+
+#pragma unroll
+  for (int s = 0; s < kMNS - 1; ++s)
+    if (s < n_st) issue(s);
+
+  const int frow = lane & 31;
+  const int g = lane >> 5;
+  const bool tail = (k1 - k0) % kMKC != 0;
+  // Wait for this wave's loads of stage st (later stages stay in flight),
+  // mask the K tail, and make stage st visible to both waves.
+  auto arrive = [&](int st) {
+    const int ahead = min(kMNS - 2, n_st - 1 - st);
+    if (ahead >= 2) wait_vmcnt<2 * LPW>();
+    else if (ahead == 1) wait_vmcnt<LPW>();
+    else wait_vmcnt<0>();
+    if (tail && st == n_st - 1) fix_tail(st);
+    // LDS reads of earlier stages and tail fix-ups are complete before the
+    // barrier, so buffers behind it may be refilled.
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    asm volatile("s_barrier" ::: "memory");
+  };
+  // Fragments of one stage: A (2 blocks) and B (4 blocks), both K halves.
+  auto read = [&](int st, v4i (&af)[2][2], v4i (&bf)[4][2]) {
+    const int8_t* As = lds + (st % kMNS) * STAGE;
+    const int8_t* Bs = DIAG ? As : As + PANEL;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int cidx = 2 * h + g;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int r = wave * 64 + m * 32 + frow;
+        af[m][h] = *reinterpret_cast<const v4i*>(As + r * kMKC + 16 * (cidx ^ swz(r)));
+      }
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        const int r = n * 32 + frow;
+        bf[n][h] = *reinterpret_cast<const v4i*>(Bs + r * kMKC + 16 * (cidx ^ swz(r)));
+      }
+    }
+  };
+  // Re products first; the -i rotation of A runs on the VALU while they
+  // execute, then the Im products.
+  auto compute = [&](const v4i (&af)[2][2], const v4i (&bf)[4][2]) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        if (DIAG && n > 2 * wave + m) continue;     // strictly upper 32 x 32 block
+        mfma64<EK>(af[m], bf[n], vr[m][n]);
+      }
+    v4i ra[2][2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) ra[m][h] = rotm4<EK>(af[m][h]);
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        if (DIAG && n > 2 * wave + m) continue;
+        mfma64<EK>(ra[m], bf[n], vi[m][n]);
+      }
+  };
+
+  for (int s = 0; s < n_st; ++s) {
+    arrive(s);
+    if (s + kMNS - 1 < n_st) issue(s + kMNS - 1);
+    v4i af[2][2], bf[4][2];
+    read(s, af, bf);
+    compute(af, bf);
+  }
+
+  float scale = 1.0f;
+  if constexpr (EK == kElemF8) scale = a.inv_scale2 ? a.inv_scale2[ch] : 1.0f;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      if (DIAG && n > 2 * wave + m) continue;
+      const int j = J * BT + n * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = I * BT + wave * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (i < a.n_in && j <= i) {
+          const int64_t off = (int64_t)split * a.out_split_stride + (int64_t)ch * a.n_products + tri_index(i, j);
+          if constexpr (EK == kElemI8) {
+            int2* pp = static_cast<int2*>(a.out) + off;
+            const int re = vr[m][n][r];
+            const int im = (i == j) ? 0 : vi[m][n][r];
+            if (a.accumulate) {
+              int2 o = *pp;
+              o.x += re;
+              o.y += im;
+              *pp = o;
+            } else {
+              *pp = make_int2(re, im);
+            }
+          } else {
+            float2* pp = static_cast<float2*>(a.out) + off;
+            const float re = vr[m][n][r] * scale;
+            const float im = (i == j) ? 0.f : vi[m][n][r] * scale;
+            if (a.accumulate) {
+              float2 o = *pp;
+              o.x += re;
+              o.y += im;
+              *pp = o;
+            } else {
+              *pp = make_float2(re, im);
+            }
+          }
+        }
+      }
+    }
+}
+
+template <int EK>
+__global__ __launch_bounds__(128, 1) void xeng_mfma_w2_kernel(XArgs a) {
+  __shared__ __attribute__((aligned(1024))) int8_t lds[kMNS * 2 * 128 * kMKC];
+  const int64_t slot = blockIdx.x / kNumXcd;
+  const int64_t item = xcd_item(blockIdx.x, a.per_xcd);
+  if (slot >= a.per_xcd || item >= a.n_items) return;
+  const int tile = (int)(item % a.n_tiles);
+  const int64_t rest = item / a.n_tiles;
+  const int split = (int)(rest % a.n_split);
+  const int ch = (int)(rest / a.n_split);
+  int I, J;
+  tile_decode(tile, I, J);
+  if (I == J) mfma_tile_w2<EK, true>(a, lds, ch, split, I, J);
+  else mfma_tile_w2<EK, false>(a, lds, ch, split, I, J);
+}
+
 template <int EK, int BT>
 __global__ __launch_bounds__(256, 2) void xeng_mfma_kernel(XArgs a) {
   __shared__ __attribute__((aligned(1024))) int8_t lds[kMNS * 2 * BT * kMKC];
@@ -308,14 +550,16 @@ hipError_t launch_xeng_mfma(const XArgs& a, int elem, int bt, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   const dim3 g((unsigned)grid), b(256);
 #define CORR_LAUNCH(EK, BT) hipLaunchKernelGGL((xeng_mfma_kernel<EK, BT>), g, b, 0, s, a)
+#define CORR_LAUNCH_W2(EK) hipLaunchKernelGGL((xeng_mfma_w2_kernel<EK>), g, dim3(128), 0, s, a)
   if (elem == kElemI8) {
-    if (bt == 128) CORR_LAUNCH(kElemI8, 128); else CORR_LAUNCH(kElemI8, 64);
+    if (bt == 128) CORR_LAUNCH_W2(kElemI8); else CORR_LAUNCH(kElemI8, 64);
   } else if (elem == kElemF16) {
-    if (bt == 128) CORR_LAUNCH(kElemF16, 128); else CORR_LAUNCH(kElemF16, 64);
+    if (bt == 128) CORR_LAUNCH_W2(kElemF16); else CORR_LAUNCH(kElemF16, 64);
   } else {
-    if (bt == 128) CORR_LAUNCH(kElemF8, 128); else CORR_LAUNCH(kElemF8, 64);
+    if (bt == 128) CORR_LAUNCH_W2(kElemF8); else CORR_LAUNCH(kElemF8, 64);
   }
 #undef CORR_LAUNCH
+#undef CORR_LAUNCH_W2
   return hipGetLastError();
 }
 
