@@ -220,7 +220,11 @@ typedef struct {
     corr_fill_fn fill;        /* produces the samples on the device, or NULL  */
     void *fill_user;          /* passed to fill                                */
     const void *d_samples;    /* used when fill == NULL: caller's device
-                                 samples, valid until the job completes       */
+                                 samples [n_channels][n_inputs][row_stride]
+                                 (e.g. a stream's ring buffer), valid until
+                                 the job completes                            */
+    int64_t row_stride;       /* samples between rows of d_samples; 0 means
+                                 n_samples (ignored with fill)                */
     void *dst;                /* int32 [n_channels][P][2] result, valid until
                                  the job completes                            */
     int32_t dst_is_device;    /* 1: dst is device memory; 0: host memory

@@ -160,7 +160,8 @@ class Scheduler:
         return corr_sched_now()
 
     def submit(self, n_inputs: int, n_channels: int, n_samples: int, dst, max_abs: int = 7,
-               fill: int = 0, fill_user: int = 0, d_samples: int = 0, t_arrival: float | None = None) -> int:
+               fill: int = 0, fill_user: int = 0, d_samples: int = 0, row_stride: int = 0,
+               t_arrival: float | None = None) -> int:
         j = corr_job_desc()
         j.n_inputs = n_inputs
         j.n_channels = n_channels
@@ -169,6 +170,7 @@ class Scheduler:
         j.fill = fill or None
         j.fill_user = fill_user or None
         j.d_samples = d_samples or None
+        j.row_stride = row_stride
         j.dst = dst.data_ptr()
         j.dst_is_device = int(dst.device.type == "cuda")
         return corr_sched_submit(self.handle, j, corr_sched_now() if t_arrival is None else t_arrival)

@@ -64,6 +64,7 @@ class corr_job_desc(ctypes.Structure):
         ("fill", ctypes.c_void_p),
         ("fill_user", ctypes.c_void_p),
         ("d_samples", ctypes.c_void_p),
+        ("row_stride", ctypes.c_int64),
         ("dst", ctypes.c_void_p),
         ("dst_is_device", ctypes.c_int32),
         ("reserved2", ctypes.c_int32),

@@ -169,7 +169,8 @@ void launch_job(corr_sched* s, Job* j) {
     j->d.fill(j->d.fill_user, j->id, base, j->d.n_channels, j->d.n_inputs, j->d.n_samples, st);
   }
   corr_status rc = corr_create(&cfg, base + j->samples_bytes, j->bytes - j->samples_bytes, st, &j->plan);
-  if (rc == CORR_OK) rc = corr_correlate(j->plan, samples, j->d.n_samples, 0);
+  const int64_t stride = j->d.fill ? 0 : j->d.row_stride;
+  if (rc == CORR_OK) rc = corr_correlate(j->plan, samples, j->d.n_samples, stride);
   if (rc == CORR_OK) rc = corr_internal_dump_async(j->plan, j->d.dst, j->d.dst_is_device, &j->n_out);
   if (rc == CORR_OK && hipLaunchHostFunc(st, on_done, j) != hipSuccess) rc = CORR_E_HIP;
   if (rc != CORR_OK) {
@@ -261,6 +262,7 @@ corr_status corr_sched_submit(corr_sched* s, const corr_job_desc* d, double t_ar
   try {
     if (!s || !d || !job_id) return CORR_E_INVAL;
     if (!d->dst || d->n_samples < 1 || (!d->fill && !d->d_samples)) return CORR_E_INVAL;
+    if (d->row_stride < 0 || (d->row_stride > 0 && d->row_stride < d->n_samples)) return CORR_E_INVAL;
     const corr_config cfg = job_config(*d);
     size_t ws = 0;
     const corr_status v = corr_workspace_bytes(&cfg, &ws);

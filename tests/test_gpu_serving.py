@@ -120,3 +120,24 @@ def test_caller_device_samples_and_host_result():
     finally:
         s.close()
     assert np.array_equal(out.numpy().astype(np.int64), oracle.xengine_ci8(x))
+
+
+def test_caller_ring_with_row_stride():
+    """Jobs read the first n_samples of each row of a wider ring buffer; the
+    samples past n_samples (filled with other values) are never used."""
+    n_in, n_ch, T, stride = 48, 5, 700, 1024
+    ring = synth.ci8(91, n_ch, n_in, stride)
+    x = np.ascontiguousarray(ring[:, :, :T])
+    rt = torch.from_numpy(ring).to(DEV)
+    out = result_buf(n_in, n_ch)
+    s = Scheduler(64 << 20, 2)
+    try:
+        with pytest.raises(CorrError) as e:
+            s.submit(n_in, n_ch, T, out, d_samples=rt.data_ptr(), row_stride=T - 1)
+        assert e.value.status == _lib.CORR_E_INVAL
+        jid = s.submit(n_in, n_ch, T, out, d_samples=rt.data_ptr(), row_stride=stride)
+        st, n, ta, td = wait(s, jid)
+        assert st == 0 and n == T
+    finally:
+        s.close()
+    assert np.array_equal(out.cpu().numpy().astype(np.int64), oracle.xengine_ci8(x))
