@@ -250,7 +250,7 @@ def main() -> int:
     achieved = ops / (kern_avg / 1e3) / 1e12
     peak = perfmodel.MI355X["int8_ops"] / 1e12
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": None, "kernel": "xeng_i8_kernel<128,true>", "kernel_ms_avg": kern_avg,
+            "traffic": None, "kernel": "corr::xeng_mfma_w2_kernel<0> (int8, 128x128 tiles, 2 waves of 64x128)", "kernel_ms_avg": kern_avg,
             "kernel_ms_min": kern_ms[0], "kernel_ms_median": kern_ms[len(kern_ms) // 2]}
 
     serve = None

@@ -462,13 +462,38 @@ __device__ __forceinline__ void mfma_tile_w2(const XArgs& a, int8_t* lds, int ch
       }
   };
 
-  for (int s = 0; s < n_st; ++s) {
-    arrive(s);
-    if (s + kMNS - 1 < n_st) issue(s + kMNS - 1);
-    v4i af[2][2], bf[4][2];
-    read(s, af, bf);
-    compute(af, bf);
+  // Fragments are double-buffered in registers: the LDS reads of stage s+1
+  // are interleaved with the MFMAs of stage s (one read after each of the
+  // first twelve MFMAs), so they run under the matrix work instead of ahead
+  // of it.  The barrier of stage s+1 follows this wave's completed reads of
+  // stage s, so stage s+4 may then be loaded into stage s's LDS buffer.
+  v4i af0[2][2], bf0[4][2], af1[2][2], bf1[4][2];
+  if (n_st > 0) {
+    arrive(0);
+    if (kMNS - 1 < n_st) issue(kMNS - 1);
+    read(0, af0, bf0);
   }
+  for (int s = 0; s + 1 < n_st; ++s) {
+    arrive(s + 1);
+    if (s + kMNS < n_st) issue(s + kMNS);
+    read(s + 1, af1, bf1);
+    compute(af0, bf0);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 20, 0);
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) af0[m][h] = af1[m][h];
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) bf0[n][h] = bf1[n][h];
+  }
+  if (n_st > 0) compute(af0, bf0);
 
   float scale = 1.0f;
   if constexpr (EK == kElemF8) scale = a.inv_scale2 ? a.inv_scale2[ch] : 1.0f;
