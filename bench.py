@@ -150,7 +150,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--cpu-channels", type=int, default=16)
+    ap.add_argument("--cpu-channels", type=int, default=64)
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
@@ -250,7 +250,7 @@ def main() -> int:
     achieved = ops / (kern_avg / 1e3) / 1e12
     peak = perfmodel.MI355X["int8_ops"] / 1e12
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": None, "kernel": "corr::xeng_mfma_w2_kernel<0> (int8, 128x128 tiles, 2 waves of 64x128)", "kernel_ms_avg": kern_avg,
+            "traffic": None, "kernel": "corr::xeng_mfma_128_kernel<0> (int8, 128x128 tiles, 4 waves of 64x64)", "kernel_ms_avg": kern_avg,
             "kernel_ms_min": kern_ms[0], "kernel_ms_median": kern_ms[len(kern_ms) // 2]}
 
     serve = None

@@ -35,7 +35,7 @@ constexpr int kMKC = 64;   // K bytes per stage
 constexpr int kMNS = 4;    // pipeline stages
 
 // 16-byte chunk c (0..3) of LDS row r lives at chunk c ^ swz(r).
-__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+__device__ __forceinline__ int swz(int r) { return (r >> 2) & 3; }
 
 // Multiply packed complex elements by i: (re, im) -> (-im, re).
 __device__ __forceinline__ int rot_i8(int w) {
@@ -313,55 +313,93 @@ __device__ __forceinline__ v4i rotm4(v4i v) {
   return r;
 }
 
-// 128 x 128 tile with two waves, each owning 64 rows x 128 columns (2 x 4
-// blocks of 32 x 32, Re and Im: 256 accumulator registers per lane).  Against
-// four waves of 64 x 64 this cuts LDS reads per MFMA by a quarter, and the
-// -i rotation moves to the A fragments (2 blocks instead of 4 per wave):
-// Im V = (-iA) B^T with -iA = (im_i, -re_i).
+// One 32 x 32 block product over 16 K bytes per lane (int8: K = 32, FP16:
+// K = 16).  FP8 blocks take both 16-byte halves at once (mfma64).
+template <int EK>
+__device__ __forceinline__ void mfma16(const v4i& a, const v4i& b, typename MAcc<EK>::T& acc) {
+  static_assert(EK != kElemF8, "FP8 products span 32 K bytes per lane");
+  if constexpr (EK == kElemI8) {
+    acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc, 0, 0, 0);
+  } else {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a), __builtin_bit_cast(v8h, b), acc, 0, 0, 0);
+  }
+}
+
+// 128 x 128 tile, four waves (2 x 2) of 64 x 64, two workgroups per CU so
+// that each SIMD holds two waves.  Per stage a wave reads 8 fragments (A and
+// B, two 32-row blocks each, two K halves) and issues 16 MFMAs (8 for FP8).
+// Fragments are double-buffered in registers: the LDS reads of stage s+1 are
+// interleaved with the MFMAs of stage s.  The barrier of stage s+1 follows
+// every wave's completed reads of stage s, so stage s+NS may then be loaded
+// into stage s's buffer.  Loads of stages that lie wholly inside the K range
+// use uniform tile bases and 32-bit per-lane offsets (LDS destinations in
+// scalar registers); the last stage clamps its addresses and is masked.
 template <int EK, bool DIAG>
-__device__ __forceinline__ void mfma_tile_w2(const XArgs& a, int8_t* lds, int ch, int split, int I, int J) {
+__device__ __forceinline__ void mfma_tile_128(const XArgs& a, int8_t* lds, int ch, int split, int I, int J) {
   constexpr int BT = 128;
   constexpr int PANEL = BT * kMKC;           // bytes per operand per stage
   constexpr int STAGE = PANEL * (DIAG ? 1 : 2);
-  constexpr int QPW = BT / 16 / 2;           // 1 KB load instructions per operand per wave
+  constexpr int QPW = BT / 16 / 4;           // 1 KB load instructions per operand per wave
   constexpr int LPW = QPW * (DIAG ? 1 : 2);  // load instructions per wave per stage
+  constexpr int NMF = EK == kElemF8 ? 8 : 16;  // MFMAs per wave per stage
   using Acc = typename MAcc<EK>::T;
 
   const int8_t* __restrict__ xc = static_cast<const int8_t*>(a.x) + (int64_t)ch * a.ch_stride_b;
   const int64_t k0 = (int64_t)split * a.k_split_bytes;
   const int64_t k1 = min(a.k_bytes, k0 + a.k_split_bytes);
   const int n_st = k1 > k0 ? (int)((k1 - k0 + kMKC - 1) / kMKC) : 0;
-  const int64_t last = ((k1 - 1) >> 4) << 4;
+  const int64_t last = ((k1 - 1) >> 4) << 4;   // last valid 16-byte chunk start
+  // Stages whose 64 bytes all lie in [k0, k1) and whose offsets fit 32 bits.
+  const int n_fast = a.row_stride_b < (int64_t(1) << 24) ? (int)((k1 - k0) / kMKC) : 0;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;                 // 0, 1: rows wave*64 .. +63
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
 
+  // This lane's part of each load instruction: LDS row lrow (of 16), chunk p.
   const int lrow = lane >> 2, p = lane & 3;
   const int8_t* gA[QPW];
   const int8_t* gB[QPW];
+  uint32_t oA[QPW], oB[QPW];
   int rowq[QPW];
+  const int8_t* tA = xc + (int64_t)(I * BT) * a.row_stride_b + k0;
+  const int8_t* tB = xc + (int64_t)(J * BT) * a.row_stride_b + k0;
 #pragma unroll
   for (int q = 0; q < QPW; ++q) {
-    const int r = (wave * QPW + q) * 16 + lrow;
+    const int r = (wave * QPW + q) * 16 + lrow;    // tile row
     rowq[q] = r;
-    const int c = p ^ swz(r);
-    gA[q] = xc + (int64_t)min(I * BT + r, a.n_in - 1) * a.row_stride_b + 16 * c;
-    if (!DIAG) gB[q] = xc + (int64_t)min(J * BT + r, a.n_in - 1) * a.row_stride_b + 16 * c;
+    const int c = p ^ swz(r);                      // global chunk this lane fetches
+    const int ra = min(I * BT + r, a.n_in - 1);
+    const int rb = min(J * BT + r, a.n_in - 1);
+    gA[q] = xc + (int64_t)ra * a.row_stride_b + 16 * c;
+    gB[q] = xc + (int64_t)rb * a.row_stride_b + 16 * c;
+    oA[q] = (uint32_t)((int64_t)(ra - I * BT) * a.row_stride_b + 16 * c);
+    oB[q] = (uint32_t)((int64_t)(rb - J * BT) * a.row_stride_b + 16 * c);
   }
   auto issue = [&](int st) {
-    int8_t* base = lds + (st % kMNS) * STAGE;
-    const int64_t kb = k0 + (int64_t)st * kMKC;
+    int8_t* base = lds + (st % kMNS) * STAGE + wave * QPW * 1024;
+    if (st < n_fast) {
+      const int8_t* ga = tA + st * kMKC;
+      const int8_t* gb = tB + st * kMKC;
 #pragma unroll
-    for (int q = 0; q < QPW; ++q) {
-      const int c = p ^ swz(rowq[q]);
-      const int64_t kk = kb + 16 * c;
-      const int64_t off = (kk <= last ? kb : last - 16 * c);
-      int8_t* dst = base + (wave * QPW + q) * 1024;
-      __builtin_amdgcn_global_load_lds(gA[q] + off, dst, 16, 0, 0);
-      if (!DIAG) __builtin_amdgcn_global_load_lds(gB[q] + off, dst + PANEL, 16, 0, 0);
+      for (int q = 0; q < QPW; ++q) {
+        __builtin_amdgcn_global_load_lds(ga + oA[q], base + q * 1024, 16, 0, 0);
+        if (!DIAG) __builtin_amdgcn_global_load_lds(gb + oB[q], base + q * 1024 + PANEL, 16, 0, 0);
+      }
+    } else {
+      const int64_t kb = k0 + (int64_t)st * kMKC;
+#pragma unroll
+      for (int q = 0; q < QPW; ++q) {
+        const int c = p ^ swz(rowq[q]);
+        const int64_t kk = kb + 16 * c;
+        const int64_t off = (kk <= last ? kb : last - 16 * c);   // keep the 16 bytes inside the row
+        __builtin_amdgcn_global_load_lds(gA[q] + off, base + q * 1024, 16, 0, 0);
+        if (!DIAG) __builtin_amdgcn_global_load_lds(gB[q] + off, base + q * 1024 + PANEL, 16, 0, 0);
+      }
     }
   };
+  // Zero / mask the chunks of stage st that reach past k1 (only the last stage).
   auto fix_tail = [&](int st) {
     int8_t* base = lds + (st % kMNS) * STAGE;
     const int64_t kb = k0 + (int64_t)st * kMKC;
@@ -388,11 +426,11 @@ __device__ __forceinline__ void mfma_tile_w2(const XArgs& a, int8_t* lds, int ch
     }
   };
 
-  Acc vr[2][4], vi[2][4];
+  Acc vr[2][2], vi[2][2];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int n = 0; n < 4; ++n)
+    for (int n = 0; n < 2; ++n)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         vr[m][n][r] = 0;
@@ -407,67 +445,75 @@ __device__ __forceinline__ void mfma_tile_w2(const XArgs& a, int8_t* lds, int ch
   const int g = lane >> 5;
   const bool tail = (k1 - k0) % kMKC != 0;
   // Wait for this wave's loads of stage st (later stages stay in flight),
-  // mask the K tail, and make stage st visible to both waves.
+  // mask the K tail, and make stage st visible to all waves.  A plain
+  // s_barrier: a fenced one would also drain the later stages' loads.
   auto arrive = [&](int st) {
     const int ahead = min(kMNS - 2, n_st - 1 - st);
     if (ahead >= 2) wait_vmcnt<2 * LPW>();
     else if (ahead == 1) wait_vmcnt<LPW>();
     else wait_vmcnt<0>();
     if (tail && st == n_st - 1) fix_tail(st);
-    // LDS reads of earlier stages and tail fix-ups are complete before the
-    // barrier, so buffers behind it may be refilled.
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     asm volatile("s_barrier" ::: "memory");
   };
-  // Fragments of one stage: A (2 blocks) and B (4 blocks), both K halves.
-  auto read = [&](int st, v4i (&af)[2][2], v4i (&bf)[4][2]) {
+  auto read = [&](int st, v4i (&af)[2][2], v4i (&bf)[2][2]) {
     const int8_t* As = lds + (st % kMNS) * STAGE;
     const int8_t* Bs = DIAG ? As : As + PANEL;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int cidx = 2 * h + g;
+      const int cidx = 2 * h + g;              // logical 16-byte chunk
 #pragma unroll
       for (int m = 0; m < 2; ++m) {
-        const int r = wave * 64 + m * 32 + frow;
+        const int r = wm * 64 + m * 32 + frow;
         af[m][h] = *reinterpret_cast<const v4i*>(As + r * kMKC + 16 * (cidx ^ swz(r)));
       }
 #pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        const int r = n * 32 + frow;
+      for (int n = 0; n < 2; ++n) {
+        const int r = wn * 64 + n * 32 + frow;
         bf[n][h] = *reinterpret_cast<const v4i*>(Bs + r * kMKC + 16 * (cidx ^ swz(r)));
       }
     }
   };
   // Re products first; the -i rotation of A runs on the VALU while they
-  // execute, then the Im products.
-  auto compute = [&](const v4i (&af)[2][2], const v4i (&bf)[4][2]) {
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        if (DIAG && n > 2 * wave + m) continue;     // strictly upper 32 x 32 block
-        mfma64<EK>(af[m], bf[n], vr[m][n]);
-      }
+  // execute, then the Im products: Im V = (-iA) B^T.  Consecutive MFMAs go to
+  // different accumulators.  Diagonal tiles compute every block (the block
+  // time is set by the full wave anyway) and store only j <= i.
+  auto compute = [&](const v4i (&af)[2][2], const v4i (&bf)[2][2]) {
     v4i ra[2][2];
+    if constexpr (EK == kElemF8) {
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+      for (int m = 0; m < 2; ++m)
 #pragma unroll
-      for (int h = 0; h < 2; ++h) ra[m][h] = rotm4<EK>(af[m][h]);
+        for (int n = 0; n < 2; ++n) mfma64<EK>(af[m], bf[n], vr[m][n]);
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+      for (int m = 0; m < 2; ++m)
 #pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        if (DIAG && n > 2 * wave + m) continue;
-        mfma64<EK>(ra[m], bf[n], vi[m][n]);
-      }
+        for (int h = 0; h < 2; ++h) ra[m][h] = rotm4<EK>(af[m][h]);
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) mfma64<EK>(ra[m], bf[n], vi[m][n]);
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int n = 0; n < 2; ++n) mfma16<EK>(af[m][h], bf[n][h], vr[m][n]);
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) ra[m][h] = rotm4<EK>(af[m][h]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int n = 0; n < 2; ++n) mfma16<EK>(ra[m][h], bf[n][h], vi[m][n]);
+    }
   };
 
-  // Fragments are double-buffered in registers: the LDS reads of stage s+1
-  // are interleaved with the MFMAs of stage s (one read after each of the
-  // first twelve MFMAs), so they run under the matrix work instead of ahead
-  // of it.  The barrier of stage s+1 follows this wave's completed reads of
-  // stage s, so stage s+4 may then be loaded into stage s's LDS buffer.
-  v4i af0[2][2], bf0[4][2], af1[2][2], bf1[4][2];
+  v4i af0[2][2], bf0[2][2], af1[2][2], bf1[2][2];
   if (n_st > 0) {
     arrive(0);
     if (kMNS - 1 < n_st) issue(kMNS - 1);
@@ -479,33 +525,34 @@ __device__ __forceinline__ void mfma_tile_w2(const XArgs& a, int8_t* lds, int ch
     read(s + 1, af1, bf1);
     compute(af0, bf0);
 #pragma unroll
-    for (int q = 0; q < 12; ++q) {
+    for (int q = 0; q < 8; ++q) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
       __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
     }
-    __builtin_amdgcn_sched_group_barrier(0x008, 20, 0);
+    if constexpr (NMF > 8) __builtin_amdgcn_sched_group_barrier(0x008, NMF - 8, 0);
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
-      for (int h = 0; h < 2; ++h) af0[m][h] = af1[m][h];
-#pragma unroll
-    for (int n = 0; n < 4; ++n)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) bf0[n][h] = bf1[n][h];
+      for (int h = 0; h < 2; ++h) {
+        af0[m][h] = af1[m][h];
+        bf0[m][h] = bf1[m][h];
+      }
   }
   if (n_st > 0) compute(af0, bf0);
 
+  if (DIAG && wm < wn) return;                 // strictly upper 64 x 64 quarter
+  // Epilogue.  32 x 32 accumulator layout: register r of lane l holds row
+  // 8*(r/4) + 4*(l/32) + r%4, column l%32.
   float scale = 1.0f;
   if constexpr (EK == kElemF8) scale = a.inv_scale2 ? a.inv_scale2[ch] : 1.0f;
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      if (DIAG && n > 2 * wave + m) continue;
-      const int j = J * BT + n * 32 + (lane & 31);
+    for (int n = 0; n < 2; ++n) {
+      const int j = J * BT + wn * 64 + n * 32 + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int i = I * BT + wave * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int i = I * BT + wm * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         if (i < a.n_in && j <= i) {
           const int64_t off = (int64_t)split * a.out_split_stride + (int64_t)ch * a.n_products + tri_index(i, j);
           if constexpr (EK == kElemI8) {
@@ -539,7 +586,7 @@ __device__ __forceinline__ void mfma_tile_w2(const XArgs& a, int8_t* lds, int ch
 }
 
 template <int EK>
-__global__ __launch_bounds__(128, 1) void xeng_mfma_w2_kernel(XArgs a) {
+__global__ __launch_bounds__(256, 2) void xeng_mfma_128_kernel(XArgs a) {
   __shared__ __attribute__((aligned(1024))) int8_t lds[kMNS * 2 * 128 * kMKC];
   const int64_t slot = blockIdx.x / kNumXcd;
   const int64_t item = xcd_item(blockIdx.x, a.per_xcd);
@@ -550,8 +597,8 @@ __global__ __launch_bounds__(128, 1) void xeng_mfma_w2_kernel(XArgs a) {
   const int ch = (int)(rest / a.n_split);
   int I, J;
   tile_decode(tile, I, J);
-  if (I == J) mfma_tile_w2<EK, true>(a, lds, ch, split, I, J);
-  else mfma_tile_w2<EK, false>(a, lds, ch, split, I, J);
+  if (I == J) mfma_tile_128<EK, true>(a, lds, ch, split, I, J);
+  else mfma_tile_128<EK, false>(a, lds, ch, split, I, J);
 }
 
 template <int EK, int BT>
@@ -575,7 +622,7 @@ hipError_t launch_xeng_mfma(const XArgs& a, int elem, int bt, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   const dim3 g((unsigned)grid), b(256);
 #define CORR_LAUNCH(EK, BT) hipLaunchKernelGGL((xeng_mfma_kernel<EK, BT>), g, b, 0, s, a)
-#define CORR_LAUNCH_W2(EK) hipLaunchKernelGGL((xeng_mfma_w2_kernel<EK>), g, dim3(128), 0, s, a)
+#define CORR_LAUNCH_W2(EK) hipLaunchKernelGGL((xeng_mfma_128_kernel<EK>), g, b, 0, s, a)
   if (elem == kElemI8) {
     if (bt == 128) CORR_LAUNCH_W2(kElemI8); else CORR_LAUNCH(kElemI8, 64);
   } else if (elem == kElemF16) {
