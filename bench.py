@@ -18,6 +18,7 @@ bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -143,6 +144,21 @@ def serving(seconds: float, warm: float, rate: float, seed: int = 5) -> dict:
             "latency_end": "integration landed in the job's device result buffer"}
 
 
+# HBM bytes per launch of the C3 int8 kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs calibrated against a 1 GiB device copy (FETCH x 2.000,
+# WRITE x 1.000); valid only for the kernel source they were taken on.
+TRAFFIC_SOURCE = os.path.join(ROOT, "paper_0906_1887_amd", "csrc", "xengine_mfma.hip")
+TRAFFIC_SHA1 = "c0dbf7c76d20684cd9fd9cce8ba2cae19083eaff"
+TRAFFIC_BYTES = {"read": 2 * 2.73853e7 * 1024, "write": 3.73021e6 * 1024}
+
+
+def measured_traffic():
+    with open(TRAFFIC_SOURCE, "rb") as fh:
+        if hashlib.sha1(fh.read()).hexdigest() != TRAFFIC_SHA1:
+            return None
+    return TRAFFIC_BYTES["read"] + TRAFFIC_BYTES["write"]
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,8 +266,9 @@ def main() -> int:
     achieved = ops / (kern_avg / 1e3) / 1e12
     peak = perfmodel.MI355X["int8_ops"] / 1e12
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": None, "kernel": "corr::xeng_mfma_128_kernel<0> (int8, 128x128 tiles, 4 waves of 64x64)", "kernel_ms_avg": kern_avg,
-            "kernel_ms_min": kern_ms[0], "kernel_ms_median": kern_ms[len(kern_ms) // 2]}
+            "traffic": measured_traffic(), "kernel": "corr::xeng_mfma_128_kernel<0> (int8, 128x128 tiles, 4 waves of 64x64)",
+            "kernel_ms_avg": kern_avg, "kernel_ms_min": kern_ms[0], "kernel_ms_median": kern_ms[len(kern_ms) // 2],
+            "algorithmic_bytes": float(N_CH * N_IN * N_T * 2 + N_CH * (N_IN * (N_IN + 1) // 2) * 8)}
 
     serve = None
     if not args.no_serving:
