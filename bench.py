@@ -257,8 +257,8 @@ def main() -> int:
         fms = e0.elapsed_time(e1) / reps
         f.close()
         fp32 = {"value": cmac / (fms / 1e3) / 1e12, "unit": "Tcmac/s", "ms": fms, "bitexact_vs_int8": same,
-                "peak_tcmac_packed": perfmodel.fp32_cmac_peak(True) / 1e12,
-                "peak_tcmac_unpacked": perfmodel.fp32_cmac_peak(False) / 1e12}
+                "peak_tcmac": perfmodel.fp32_cmac_peak() / 1e12,
+                "frac": cmac / (fms / 1e3) / perfmodel.fp32_cmac_peak()}
     del out_dev
 
     # roofline of the dominant kernel: int8 MFMA ops (4 real MACs = 8 ops per CMAC)

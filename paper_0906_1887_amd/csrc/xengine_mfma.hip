@@ -20,6 +20,8 @@
 // zeroed in LDS before use.  Tiles are numbered channel-major and remapped
 // from blockIdx.x so that each XCD (and its L2) runs a contiguous range of
 // channels.
+#include <type_traits>
+
 #include "common.h"
 #include "launch.h"
 
@@ -478,13 +480,16 @@ __device__ __forceinline__ void mfma_tile_128(const XArgs& a, int8_t* lds, int c
   // execute, then the Im products: Im V = (-iA) B^T.  Consecutive MFMAs go to
   // different accumulators.  Diagonal tiles compute every block (the block
   // time is set by the full wave anyway) and store only j <= i.
-  auto compute = [&](const v4i (&af)[2][2], const v4i (&bf)[2][2]) {
+  // SK: a diagonal wave of a diagonal tile skips its strictly upper block (m 0, n 1).
+  auto compute = [&](auto sk, const v4i (&af)[2][2], const v4i (&bf)[2][2]) {
+    constexpr bool SK = decltype(sk)::value;
     v4i ra[2][2];
     if constexpr (EK == kElemF8) {
 #pragma unroll
       for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int n = 0; n < 2; ++n) mfma64<EK>(af[m], bf[n], vr[m][n]);
+        for (int n = 0; n < 2; ++n)
+          if (!(SK && m == 0 && n == 1)) mfma64<EK>(af[m], bf[n], vr[m][n]);
 #pragma unroll
       for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -492,14 +497,16 @@ __device__ __forceinline__ void mfma_tile_128(const XArgs& a, int8_t* lds, int c
 #pragma unroll
       for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int n = 0; n < 2; ++n) mfma64<EK>(ra[m], bf[n], vi[m][n]);
+        for (int n = 0; n < 2; ++n)
+          if (!(SK && m == 0 && n == 1)) mfma64<EK>(ra[m], bf[n], vi[m][n]);
     } else {
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int m = 0; m < 2; ++m)
 #pragma unroll
-          for (int n = 0; n < 2; ++n) mfma16<EK>(af[m][h], bf[n][h], vr[m][n]);
+          for (int n = 0; n < 2; ++n)
+            if (!(SK && m == 0 && n == 1)) mfma16<EK>(af[m][h], bf[n][h], vr[m][n]);
 #pragma unroll
       for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -509,38 +516,52 @@ __device__ __forceinline__ void mfma_tile_128(const XArgs& a, int8_t* lds, int c
 #pragma unroll
         for (int m = 0; m < 2; ++m)
 #pragma unroll
-          for (int n = 0; n < 2; ++n) mfma16<EK>(ra[m][h], bf[n][h], vi[m][n]);
+          for (int n = 0; n < 2; ++n)
+            if (!(SK && m == 0 && n == 1)) mfma16<EK>(ra[m][h], bf[n][h], vi[m][n]);
     }
   };
 
-  v4i af0[2][2], bf0[2][2], af1[2][2], bf1[2][2];
   if (n_st > 0) {
     arrive(0);
     if (kMNS - 1 < n_st) issue(kMNS - 1);
-    read(0, af0, bf0);
   }
-  for (int s = 0; s + 1 < n_st; ++s) {
-    arrive(s + 1);
-    if (s + kMNS < n_st) issue(s + kMNS);
-    read(s + 1, af1, bf1);
-    compute(af0, bf0);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
-      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+  // In a diagonal tile the wave of the strictly upper 64 x 64 quarter only
+  // loads its share of the panel and keeps the barriers.
+  if (DIAG && wm < wn) {
+    for (int s = 0; s + 1 < n_st; ++s) {
+      arrive(s + 1);
+      if (s + kMNS < n_st) issue(s + kMNS);
     }
-    if constexpr (NMF > 8) __builtin_amdgcn_sched_group_barrier(0x008, NMF - 8, 0);
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        af0[m][h] = af1[m][h];
-        bf0[m][h] = bf1[m][h];
-      }
+    return;
   }
-  if (n_st > 0) compute(af0, bf0);
+  auto run = [&](auto sk) {
+    constexpr int NM = (DIAG && decltype(sk)::value) ? NMF * 3 / 4 : NMF;   // MFMAs per stage
+    v4i af0[2][2], bf0[2][2], af1[2][2], bf1[2][2];
+    if (n_st > 0) read(0, af0, bf0);
+    for (int s = 0; s + 1 < n_st; ++s) {
+      arrive(s + 1);
+      if (s + kMNS < n_st) issue(s + kMNS);
+      read(s + 1, af1, bf1);
+      compute(sk, af0, bf0);
+#pragma unroll
+      for (int q = 0; q < (NM < 8 ? NM : 8); ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+      }
+      if constexpr (NM > 8) __builtin_amdgcn_sched_group_barrier(0x008, NM - 8, 0);
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          af0[m][h] = af1[m][h];
+          bf0[m][h] = bf1[m][h];
+        }
+    }
+    if (n_st > 0) compute(sk, af0, bf0);
+  };
+  if (DIAG && wm == wn) run(std::true_type{});
+  else run(std::false_type{});
 
-  if (DIAG && wm < wn) return;                 // strictly upper 64 x 64 quarter
   // Epilogue.  32 x 32 accumulator layout: register r of lane l holds row
   // 8*(r/4) + 4*(l/32) + r%4, column l%32.
   float scale = 1.0f;

@@ -89,6 +89,8 @@ def int8_cmac_peak() -> float:
     return MI355X["int8_ops"] / 2.0 / REAL_MACS_PER_CMAC
 
 
-def fp32_cmac_peak(packed: bool = True) -> float:
-    f = MI355X["fp32_vec_flops"] / FLOPS_PER_CMAC
-    return f if packed else f / 2.0
+def fp32_cmac_peak() -> float:
+    """Vector FP32 ceiling in CMAC/s (MI355X's published 157.3 TFLOP/s, 8 flops
+    per CMAC).  gfx950 reaches more than half of it with plain v_fma_f32, so no
+    separate packed / unpacked figure is kept."""
+    return MI355X["fp32_vec_flops"] / FLOPS_PER_CMAC
