@@ -59,6 +59,18 @@ def test_edge_shapes_ci8(engine):
             assert np.array_equal(got, want), (engine, n_in, n_ch, T)
 
 
+def test_wide_arrays_all_tile_kinds():
+    """3 to 9 row blocks of 128 inputs (odd and even block counts, ragged last
+    block) reach every kind of work item of the 128-row engine: tile pairs
+    below the diagonal, a pair ending on the diagonal, and two diagonal tiles
+    of different rows in one workgroup; T = 1500 on two channels also splits
+    K.  int8 engine against the oracle."""
+    for n_in, T in ((260, 129), (390, 70), (520, 1500), (777, 65), (1100, 200)):
+        say(f"[xengine i8 ci8] n_in={n_in} n_ch=2 T={T}")
+        x = synth.ci8(seed=n_in + 31 * T, n_channels=2, n_inputs=n_in, n_samples=T)
+        assert np.array_equal(gpu_vis(x, "i8"), oracle.xengine_ci8(x)), (n_in, T)
+
+
 def test_edge_shapes_cf32_fp32():
     for n_in in (1, 17, 64, 65, 129):
         for T in (1, 7, 64, 100):
