@@ -159,6 +159,116 @@ def measured_traffic():
     return TRAFFIC_BYTES["read"] + TRAFFIC_BYTES["write"]
 
 
+def time_events(fn, reps, stream):
+    """Average ms of fn() over reps back-to-back calls, HIP events on stream."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def other_configs(dev, stream):
+    """C1, C2 and C4 at their full sizes: one timed figure per step of the
+    path, against its roofline (inputs made on the device; timing only, the
+    parity of these configurations is checked by the GPU tests)."""
+    import torch
+    import synth
+    from paper_0906_1887_amd import Correlator, perfmodel
+    hbm = perfmodel.MI355X["hbm_Bps"]
+    out = {}
+
+    # C1: plain FP32 X-engine, N_I=64, 128 channels, 1000 samples, complex float32
+    n_in, n_ch, T = 64, 128, 1000
+    x8 = torch.empty((n_ch, n_in, T, 2), dtype=torch.int8, device=dev)
+    synth.DeviceGen().fill_ci8(x8.data_ptr(), n_ch, n_in, T, 1, stream=stream.cuda_stream)
+    xf = x8.float()
+    c = Correlator(n_in, n_ch, engine="fp32", sample_type="cf32", max_abs=7, device=str(dev))
+    cm = perfmodel.xengine_cmac(n_ch, n_in, T)
+
+    def c1():
+        c.correlate(xf)
+        c.dump(0)
+    c1()
+    ms = time_events(c1, 200, stream)
+    out["c1_fp32_plain"] = {"ms_per_integration": ms, "tcmac_s": cm / (ms / 1e3) / 1e12,
+                            "frac_of_fp32_peak": cm / (ms / 1e3) / perfmodel.fp32_cmac_peak(),
+                            "note": "X + accumulator reset per integration, 200 back-to-back"}
+    c.close()
+    del x8, xf
+
+    # C2: F-stage (256-pt real FFT, requantise, corner turn) and X on the ring, N_I=64
+    n_in, nb = 64, 10000
+    s_req = float(torch.tensor(2.0 / (16.0 * 128 ** 0.5), dtype=torch.float32))
+    g = torch.Generator(device=dev).manual_seed(2)
+    volt = torch.clamp(torch.round(16.0 * torch.randn((nb * 256, n_in), device=dev, generator=g)), -128, 127)
+    volt = volt.to(torch.int8).contiguous()
+    c = Correlator(n_in, 128, engine="i8", fft_size=256, max_abs=7, requant_scale=s_req, ring_samples=nb,
+                   device=str(dev))
+    seq = [0]
+
+    def f():
+        c.channelise(volt, first_seq=seq[0])
+        seq[0] += nb
+        c.correlate(None)
+        c.dump(0)
+    f()
+    reps = 20
+    e = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+          torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    for k in range(reps):
+        e[k][0].record(stream)
+        c.channelise(volt, first_seq=seq[0])
+        seq[0] += nb
+        e[k][1].record(stream)
+        c.correlate(None)
+        e[k][2].record(stream)
+        c.dump(0)
+    torch.cuda.synchronize()
+    f_ms = sum(a.elapsed_time(b) for a, b, _ in e) / reps
+    x_ms = sum(b.elapsed_time(d) for _, b, d in e) / reps
+    f_bytes = nb * 256 * n_in + 128 * n_in * nb * 2
+    x_bytes = 128 * n_in * nb * 2 + 128 * (n_in * (n_in + 1) // 2) * 8
+    cm = perfmodel.xengine_cmac(128, n_in, nb)
+    out["c2_fx"] = {"fstage_ms": f_ms, "fstage_GB_s": f_bytes / (f_ms / 1e3) / 1e9,
+                    "fstage_frac_of_hbm": f_bytes / (f_ms / 1e3) / hbm,
+                    "xengine_ms": x_ms, "xengine_GB_s": x_bytes / (x_ms / 1e3) / 1e9,
+                    "xengine_frac_of_hbm": x_bytes / (x_ms / 1e3) / hbm,
+                    "xengine_tcmac_s": cm / (x_ms / 1e3) / 1e12,
+                    "note": "per integration of 10000 blocks x 64 inputs; algorithmic bytes: F 1 B in + 2 B out "
+                            "per sample, X 2 B per sample in + 8 B per product out"}
+    c.close()
+    del volt
+
+    # C4: FP16 / FP8 staging + matrix-core X-engine, N_I=256, 1024 channels, 4096 samples
+    n_in, n_ch, T = 256, 1024, 4096
+    g = torch.Generator(device=dev).manual_seed(4)
+    xf = torch.randn((n_ch, n_in, T, 2), device=dev, generator=g)
+    cm = perfmodel.xengine_cmac(n_ch, n_in, T)
+    for engine, peak, sb in (("f16", perfmodel.MI355X["fp16_flops"], 4), ("f8", perfmodel.MI355X["fp8_flops"], 2)):
+        c = Correlator(n_in, n_ch, engine=engine, sample_type="cf32", max_abs=0, ring_samples=T, device=str(dev))
+
+        def f4():
+            c.correlate(xf, T)
+            c.dump(0)
+        f4()
+        ms = time_events(f4, 5, stream)
+        nbytes = n_ch * n_in * T * (8 + 2 * sb) + n_ch * (n_in * (n_in + 1) // 2) * 8
+        out[f"c4_{engine}"] = {"ms": ms, "tcmac_s": cm / (ms / 1e3) / 1e12,
+                               "frac_of_mfma_peak": cm * 8 / (ms / 1e3) / peak,
+                               "GB_s": nbytes / (ms / 1e3) / 1e9, "frac_of_hbm": nbytes / (ms / 1e3) / hbm,
+                               "note": "FP32 read by the converter, staged write and read, output write"}
+        c.close()
+    del xf
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +279,7 @@ def main() -> int:
     ap.add_argument("--cpu-channels", type=int, default=64)
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-other-configs", action="store_true")
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
                     help="copy: only a 1 GiB device-to-device copy, the known-size reference for "
                          "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -278,6 +389,13 @@ def main() -> int:
         serve = serving(args.serve_seconds, warm=1.0, rate=200.0)
         x = None
 
+    others = None
+    if not args.no_other_configs:
+        log("C1, C2, C4")
+        x = None
+        torch.cuda.empty_cache()
+        others = other_configs(dev, stream)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
@@ -309,6 +427,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "fp32_plain": fp32,
         "serving": serve,
+        "other_configs": others,
         "dump_ms": {"device": dump_dev_ms, "host_pinned": dump_host_ms, "bytes": N_CH * N_IN * (N_IN + 1) // 2 * 8},
         "paper_context": "60x over one CPU thread at 32 antennas on 2008 NVIDIA hardware (abstract); context only",
     }

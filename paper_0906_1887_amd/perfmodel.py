@@ -22,7 +22,7 @@ MI355X = {
     "int8_ops": 5.0e15,      # dense int8 MFMA, ops/s (1 MAC = 2 ops)
     "fp8_flops": 5.0e15,
     "fp16_flops": 2.5e15,
-    "fp32_vec_flops": 157.3e12,  # with packed FP32 FMA
+    "fp32_vec_flops": 157.3e12,  # published vector FP32 rate
     "fp64_vec_flops": 78.6e12,
 }
 
