@@ -74,7 +74,9 @@ typedef enum {
                                  input staged with a power-of-two per-channel
                                  scale s_c: the largest with s_c * max|x| <=
                                  448, kept in [2^-60, 2^60]; the epilogue
-                                 multiplies by 1/s_c^2)                    */
+                                 multiplies by 1/s_c^2).  F16 and F8 plans
+                                 with more than 65535 inputs or channels
+                                 return CORR_E_UNSUPPORTED.                */
 } corr_engine_t;
 
 typedef struct {

@@ -62,7 +62,7 @@ corr_status validate(const corr_config* c) {
     // float samples staged to FP16 / FP8 in chunks of ring_samples
     if (c->sample_type != CORR_CF32 || c->max_abs != 0 || c->fft_size != 0) return CORR_E_INVAL;
     if (c->ring_samples < 1) return CORR_E_INVAL;
-    if (c->n_channels > 65535) return CORR_E_UNSUPPORTED;
+    if (c->n_channels > 65535 || c->n_inputs > 65535) return CORR_E_UNSUPPORTED;
   }
   if (c->engine == CORR_X_I8) {
     if (c->sample_type != CORR_CI8 && c->fft_size == 0) return CORR_E_INVAL;

@@ -24,7 +24,6 @@ constexpr int kFBlk = 16;         // blocks per workgroup
 constexpr int kFIn = 8;           // inputs per workgroup (4 pairs)
 constexpr int kFPairs = kFIn / 2;
 constexpr int kFFtPerRound = 16;  // 256 threads / 16 lanes per FFT
-constexpr int kFRounds = kFBlk * kFPairs / kFFtPerRound;
 constexpr int kFSRow = 17;        // padded row of the 16x16 exchange
 
 struct FArgs {
@@ -103,10 +102,10 @@ __device__ __forceinline__ int8_t requant(float x, float s, float m) {
   return (int8_t)(int)r;
 }
 
-__global__ __launch_bounds__(256) void fstage_kernel(FArgs a) {
+__global__ __launch_bounds__(256, 2) void fstage_kernel(FArgs a) {
   __shared__ __attribute__((aligned(16))) int8_t vin[kFBlk * kFN][kFIn];            // 32 KB
   __shared__ __attribute__((aligned(16))) float2 S[kFFtPerRound][kFSRow * 16];       // 34 KB
-  __shared__ __attribute__((aligned(16))) uint16_t O[kFCh][kFIn][kFBlk];             // 32 KB
+  __shared__ __attribute__((aligned(16))) uint16_t O[kFCh][2][kFBlk];                // 8 KB
   __shared__ float2 tw[kFN];
 
   const int tid = threadIdx.x;
@@ -116,37 +115,43 @@ __global__ __launch_bounds__(256) void fstage_kernel(FArgs a) {
 
   tw[tid] = a.twiddle[tid];
 
-  // Load [16 blocks * 256 samples][8 inputs] (zero outside).
-  for (int r = tid; r < kFBlk * kFN; r += 256) {
-    const int64_t t = b0 * kFN + r;
-    uint2 w = make_uint2(0u, 0u);
-    if (t < a.n_blocks * kFN) {
-      const int8_t* p = a.volt + t * a.n_in + i0;
-      if (a.vec_in) {
-        w = *reinterpret_cast<const uint2*>(p);
-      } else {
-        uint8_t bytes[8];
+  // Load [16 blocks * 256 samples][8 inputs] (zero outside): all 16 loads of
+  // a thread are in flight before the first LDS write.
+  constexpr int kLoads = kFBlk * kFN / 256;
+  if (a.vec_in && b0 + kFBlk <= a.n_blocks) {
+    uint2 w[kLoads];
+    const int8_t* p = a.volt + (b0 * kFN + tid) * a.n_in + i0;
+#pragma unroll
+    for (int q = 0; q < kLoads; ++q) w[q] = *reinterpret_cast<const uint2*>(p + (int64_t)q * 256 * a.n_in);
+#pragma unroll
+    for (int q = 0; q < kLoads; ++q) *reinterpret_cast<uint2*>(&vin[tid + 256 * q][0]) = w[q];
+  } else {
+    for (int r = tid; r < kFBlk * kFN; r += 256) {
+      const int64_t t = b0 * kFN + r;
+      uint8_t bytes[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (t < a.n_blocks * kFN) {
+        const int8_t* p = a.volt + t * a.n_in + i0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) bytes[q] = (i0 + q < a.n_in) ? (uint8_t)p[q] : 0u;
-        w.x = bytes[0] | (bytes[1] << 8) | (bytes[2] << 16) | ((uint32_t)bytes[3] << 24);
-        w.y = bytes[4] | (bytes[5] << 8) | (bytes[6] << 16) | ((uint32_t)bytes[7] << 24);
       }
+      uint2 w;
+      w.x = bytes[0] | (bytes[1] << 8) | (bytes[2] << 16) | ((uint32_t)bytes[3] << 24);
+      w.y = bytes[4] | (bytes[5] << 8) | (bytes[6] << 16) | ((uint32_t)bytes[7] << 24);
+      *reinterpret_cast<uint2*>(&vin[r][0]) = w;
     }
-    *reinterpret_cast<uint2*>(&vin[r][0]) = w;
   }
   __syncthreads();
 
-  const int f = tid >> 4;     // FFT slot in this round
+  // One round per input pair: FFT slot f transforms block f of the pair.
+  const int f = tid >> 4;     // block of this FFT
   const int l = tid & 15;     // lane within the FFT
-  for (int round = 0; round < kFRounds; ++round) {
-    const int g = round * kFFtPerRound + f;
-    const int blk = g / kFPairs;
-    const int pr = g % kFPairs;
+  const int64_t nb = min((int64_t)kFBlk, a.n_blocks - b0);
+  for (int pr = 0; pr < kFPairs; ++pr) {
     // Pass 1: lane n1 = l transforms z[n1 + 16 n2] over n2.
     float2 x[16], X[16];
 #pragma unroll
     for (int n2 = 0; n2 < 16; ++n2) {
-      const int r = blk * kFN + l + 16 * n2;
+      const int r = f * kFN + l + 16 * n2;
       x[n2] = make_float2((float)vin[r][2 * pr], (float)vin[r][2 * pr + 1]);
     }
     dft16(x, X);
@@ -162,7 +167,7 @@ __global__ __launch_bounds__(256) void fstage_kernel(FArgs a) {
     for (int k1 = 0; k1 < 16; ++k1) S[f][l + 16 * k1] = X[k1];
     __syncthreads();
     // Split the two real inputs and requantise channels k < 128.
-    const int64_t blk_g = b0 + blk;
+    const int64_t blk_g = b0 + f;
 #pragma unroll
     for (int k1 = 0; k1 < 8; ++k1) {
       const int k = l + 16 * k1;
@@ -170,12 +175,10 @@ __global__ __launch_bounds__(256) void fstage_kernel(FArgs a) {
       const float2 zm = S[f][(kFN - k) & (kFN - 1)];
       const float2 xa = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
       const float2 xb = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
-      const uint16_t qa = (uint16_t)(uint8_t)requant(xa.x, a.scale, a.max_abs) |
-                          ((uint16_t)(uint8_t)requant(xa.y, a.scale, a.max_abs) << 8);
-      const uint16_t qb = (uint16_t)(uint8_t)requant(xb.x, a.scale, a.max_abs) |
-                          ((uint16_t)(uint8_t)requant(xb.y, a.scale, a.max_abs) << 8);
-      O[k][2 * pr][blk] = qa;
-      O[k][2 * pr + 1][blk] = qb;
+      O[k][0][f] = (uint16_t)(uint8_t)requant(xa.x, a.scale, a.max_abs) |
+                   ((uint16_t)(uint8_t)requant(xa.y, a.scale, a.max_abs) << 8);
+      O[k][1][f] = (uint16_t)(uint8_t)requant(xb.x, a.scale, a.max_abs) |
+                   ((uint16_t)(uint8_t)requant(xb.y, a.scale, a.max_abs) << 8);
       if (a.dbg != nullptr && blk_g < a.n_blocks) {
         const int ia = i0 + 2 * pr, ib = ia + 1;
         if (ia < a.n_in)
@@ -185,22 +188,24 @@ __global__ __launch_bounds__(256) void fstage_kernel(FArgs a) {
       }
     }
     __syncthreads();
-  }
-
-  // Write O[k][input][16 blocks] to ring[k][i0 + input][t_offset + b0 ..].
-  const int64_t nb = min((int64_t)kFBlk, a.n_blocks - b0);
-  for (int row = tid; row < kFCh * kFIn; row += 256) {
-    const int k = row / kFIn, il = row % kFIn;
-    const int i = i0 + il;
-    if (i >= a.n_in) continue;
-    uint16_t* dst = reinterpret_cast<uint16_t*>(a.ring) + ((int64_t)k * a.n_in + i) * a.ring_stride + a.t_offset + b0;
-    if (a.vec_out && nb == kFBlk) {
-      const uint4* src = reinterpret_cast<const uint4*>(&O[k][il][0]);
-      reinterpret_cast<uint4*>(dst)[0] = src[0];
-      reinterpret_cast<uint4*>(dst)[1] = src[1];
-    } else {
-      for (int q = 0; q < nb; ++q) dst[q] = O[k][il][q];
+    // Write O[k][2 inputs][16 blocks] to ring[k][input][t_offset + b0 ..]:
+    // one 32-byte row segment per thread.
+    {
+      const int k = tid >> 1, il = tid & 1;
+      const int i = i0 + 2 * pr + il;
+      if (i < a.n_in) {
+        uint16_t* dst =
+            reinterpret_cast<uint16_t*>(a.ring) + ((int64_t)k * a.n_in + i) * a.ring_stride + a.t_offset + b0;
+        if (a.vec_out && nb == kFBlk) {
+          const uint4* src = reinterpret_cast<const uint4*>(&O[k][il][0]);
+          reinterpret_cast<uint4*>(dst)[0] = src[0];
+          reinterpret_cast<uint4*>(dst)[1] = src[1];
+        } else {
+          for (int q = 0; q < nb; ++q) dst[q] = O[k][il][q];
+        }
+      }
     }
+    __syncthreads();
   }
 }
 

@@ -14,26 +14,47 @@
 namespace corr {
 
 // Max |re|, |im| per channel (as float bits; non-negative floats order like
-// their bit patterns), one atomicMax per workgroup.
+// their bit patterns), one atomicMax per workgroup.  VEC: rows start 16-byte
+// aligned, so each lane reads two complex samples (one float4) at a time.
+template <bool VEC>
 __global__ __launch_bounds__(256) void absmax_kernel(const float* __restrict__ x, int64_t n_in, int64_t n_t,
                                                       int64_t row_stride, int64_t rows_per_wg,
                                                       uint32_t* __restrict__ m_bits) {
   const int64_t ch = blockIdx.y;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
   const int64_t r1 = min(n_in, r0 + rows_per_wg);
+  const int tid = threadIdx.x;
   float m = 0.f;
   for (int64_t r = r0; r < r1; ++r) {
     const float* row = x + ((ch * n_in + r) * row_stride) * 2;
-    for (int64_t k = threadIdx.x; k < 2 * n_t; k += blockDim.x) m = fmaxf(m, fabsf(row[k]));
+    if (VEC) {
+      const float4* rv = reinterpret_cast<const float4*>(row);
+      const int64_t nv = n_t / 2;
+      int64_t u = tid;
+      for (; u + 768 < nv; u += 1024) {
+        const float4 a = rv[u], b = rv[u + 256], c = rv[u + 512], d = rv[u + 768];
+        m = fmaxf(m, fmaxf(fmaxf(fmaxf(fabsf(a.x), fabsf(a.y)), fmaxf(fabsf(a.z), fabsf(a.w))),
+                           fmaxf(fmaxf(fabsf(b.x), fabsf(b.y)), fmaxf(fabsf(b.z), fabsf(b.w)))));
+        m = fmaxf(m, fmaxf(fmaxf(fmaxf(fabsf(c.x), fabsf(c.y)), fmaxf(fabsf(c.z), fabsf(c.w))),
+                           fmaxf(fmaxf(fabsf(d.x), fabsf(d.y)), fmaxf(fabsf(d.z), fabsf(d.w)))));
+      }
+      for (; u < nv; u += 256) {
+        const float4 a = rv[u];
+        m = fmaxf(m, fmaxf(fmaxf(fabsf(a.x), fabsf(a.y)), fmaxf(fabsf(a.z), fabsf(a.w))));
+      }
+      if ((n_t & 1) && tid == 0) m = fmaxf(m, fmaxf(fabsf(row[2 * n_t - 2]), fabsf(row[2 * n_t - 1])));
+    } else {
+      for (int64_t k = tid; k < 2 * n_t; k += 256) m = fmaxf(m, fabsf(row[k]));
+    }
   }
   __shared__ float red[256];
-  red[threadIdx.x] = m;
+  red[tid] = m;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    if (tid < w) red[tid] = fmaxf(red[tid], red[tid + w]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicMax(&m_bits[ch], __float_as_uint(red[0]));
+  if (tid == 0) atomicMax(&m_bits[ch], __float_as_uint(red[0]));
 }
 
 // The exponent is clamped to [-60, 60] (so 1/s^2 stays a normal float) and
@@ -48,28 +69,35 @@ __device__ __forceinline__ float e4m3_scale(float m) {
   return s;
 }
 
-// One thread converts 4 complex samples of one row.  out rows have
-// out_stride samples; elem 1: FP16 (4 bytes per sample), 2: FP8 (2 bytes).
-template <int ELEM>
+// One thread converts 4 complex samples of one row (grid: sample groups x
+// rows x channels).  Out rows have out_stride samples; FP16: 4 bytes per
+// sample, FP8: 2.  VEC: the row starts 16-byte aligned, so full groups are
+// read as two float4.
+template <int ELEM, bool VEC>
 __global__ __launch_bounds__(256) void lowp_convert_kernel(const float* __restrict__ x, int64_t n_in, int64_t n_t,
                                                            int64_t row_stride, int64_t out_stride,
                                                            const uint32_t* __restrict__ m_bits, void* __restrict__ out,
                                                            float* __restrict__ inv_scale2) {
-  const int64_t ch = blockIdx.y;
-  const int64_t groups = (n_t + 3) / 4;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ch = blockIdx.z;
+  const int64_t r = blockIdx.y;
+  const int64_t t0 = 4 * ((int64_t)blockIdx.x * 256 + threadIdx.x);
   float s = 1.f;
   if (ELEM == kElemF8) {
     s = e4m3_scale(__uint_as_float(m_bits[ch]));
-    if (gid == 0) inv_scale2[ch] = 1.f / (s * s);
+    if (r == 0 && t0 == 0) inv_scale2[ch] = 1.f / (s * s);
   }
-  if (gid >= n_in * groups) return;
-  const int64_t r = gid / groups;
-  const int64_t t0 = (gid - r * groups) * 4;
+  if (t0 >= n_t) return;
   const float* src = x + ((ch * n_in + r) * row_stride + t0) * 2;
   float v[8];
+  if (VEC && t0 + 4 <= n_t) {
+    const float4 a = reinterpret_cast<const float4*>(src)[0];
+    const float4 b = reinterpret_cast<const float4*>(src)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
 #pragma unroll
-  for (int q = 0; q < 8; ++q) v[q] = (t0 + q / 2 < n_t) ? src[q] : 0.f;
+    for (int q = 0; q < 8; ++q) v[q] = (t0 + q / 2 < n_t) ? src[q] : 0.f;
+  }
   if (ELEM == kElemF16) {
     uint32_t w[4];
 #pragma unroll
@@ -103,26 +131,35 @@ __global__ __launch_bounds__(256) void lowp_convert_kernel(const float* __restri
 
 hipError_t launch_lowp_stage(const LowpCall& c, hipStream_t s) {
   if (c.n_ch <= 0 || c.n_in <= 0 || c.n_t <= 0) return hipSuccess;
-  if (c.n_ch > 65535) return hipErrorInvalidValue;
+  if (c.n_ch > 65535 || c.n_in > 65535) return hipErrorInvalidValue;
+  const bool vec = (reinterpret_cast<uintptr_t>(c.x) % 16 == 0) && (c.row_stride % 2 == 0);
   hipError_t e;
   if (c.elem == kElemF8) {
     e = launch_fill_zero(c.m_bits, (c.n_ch * 4 + 15) / 16 * 16, s);
     if (e != hipSuccess) return e;
     const int64_t rows_per_wg = 4;
     const dim3 g((unsigned)((c.n_in + rows_per_wg - 1) / rows_per_wg), (unsigned)c.n_ch);
-    hipLaunchKernelGGL(absmax_kernel, g, dim3(256), 0, s, c.x, (int64_t)c.n_in, c.n_t, c.row_stride, rows_per_wg,
-                       c.m_bits);
+    if (vec)
+      hipLaunchKernelGGL(absmax_kernel<true>, g, dim3(256), 0, s, c.x, (int64_t)c.n_in, c.n_t, c.row_stride,
+                         rows_per_wg, c.m_bits);
+    else
+      hipLaunchKernelGGL(absmax_kernel<false>, g, dim3(256), 0, s, c.x, (int64_t)c.n_in, c.n_t, c.row_stride,
+                         rows_per_wg, c.m_bits);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const int64_t groups = (c.n_t + 3) / 4;
-  const dim3 g((unsigned)((c.n_in * groups + 255) / 256), (unsigned)c.n_ch);
-  if (c.elem == kElemF16)
-    hipLaunchKernelGGL(lowp_convert_kernel<kElemF16>, g, dim3(256), 0, s, c.x, (int64_t)c.n_in, c.n_t,
-                       c.row_stride, c.out_stride, c.m_bits, c.out, c.inv_scale2);
-  else
-    hipLaunchKernelGGL(lowp_convert_kernel<kElemF8>, g, dim3(256), 0, s, c.x, (int64_t)c.n_in, c.n_t,
-                       c.row_stride, c.out_stride, c.m_bits, c.out, c.inv_scale2);
+  const int64_t gx = ((c.n_t + 3) / 4 + 255) / 256;
+  if (gx > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const dim3 g((unsigned)gx, (unsigned)c.n_in, (unsigned)c.n_ch);
+#define CORR_CONVERT(EL, V)                                                                                   \
+  hipLaunchKernelGGL((lowp_convert_kernel<EL, V>), g, dim3(256), 0, s, c.x, (int64_t)c.n_in, c.n_t, c.row_stride, \
+                     c.out_stride, c.m_bits, c.out, c.inv_scale2)
+  if (c.elem == kElemF16) {
+    if (vec) CORR_CONVERT(kElemF16, true); else CORR_CONVERT(kElemF16, false);
+  } else {
+    if (vec) CORR_CONVERT(kElemF8, true); else CORR_CONVERT(kElemF8, false);
+  }
+#undef CORR_CONVERT
   return hipGetLastError();
 }
 
