@@ -148,8 +148,8 @@ def serving(seconds: float, warm: float, rate: float, seed: int = 5) -> dict:
 # WRITE_SIZE runs calibrated against a 1 GiB device copy (FETCH x 2.000,
 # WRITE x 1.000); valid only for the kernel source they were taken on.
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_0906_1887_amd", "csrc", "xengine_mfma.hip")
-TRAFFIC_SHA1 = "c0dbf7c76d20684cd9fd9cce8ba2cae19083eaff"
-TRAFFIC_BYTES = {"read": 2 * 2.73853e7 * 1024, "write": 3.73021e6 * 1024}
+TRAFFIC_SHA1 = "a546562f74c4f33e2a3c5aeb24d11b8fb0cefdbf"
+TRAFFIC_BYTES = {"read": 2 * 2.9245e7 * 1024, "write": 3.74832e6 * 1024}
 
 
 def measured_traffic():
