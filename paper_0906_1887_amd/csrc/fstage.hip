@@ -40,6 +40,8 @@ struct FArgs {
   float max_abs;
   int32_t vec_in;          // 1: n_in % 8 == 0 and volt 8-byte aligned
   int32_t vec_out;         // 1: t_offset % 8 == 0 and ring_stride % 8 == 0
+  int64_t n_items;         // block groups x input groups
+  int64_t per_xcd;         // ceil(n_items / 8)
 };
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -109,8 +111,12 @@ __global__ __launch_bounds__(256, 2) void fstage_kernel(FArgs a) {
   __shared__ float2 tw[kFN];
 
   const int tid = threadIdx.x;
-  const int ig = blockIdx.x % a.n_ig;
-  const int64_t b0 = (int64_t)(blockIdx.x / a.n_ig) * kFBlk;
+  // The n_ig workgroups of one block group read the same input rows; the
+  // XCD remap puts them on one XCD (one L2), one after another.
+  const int64_t item = xcd_item(blockIdx.x, a.per_xcd);
+  if ((int64_t)(blockIdx.x / kNumXcd) >= a.per_xcd || item >= a.n_items) return;
+  const int ig = (int)(item % a.n_ig);
+  const int64_t b0 = (item / a.n_ig) * kFBlk;
   const int i0 = ig * kFIn;
 
   tw[tid] = a.twiddle[tid];
@@ -146,17 +152,22 @@ __global__ __launch_bounds__(256, 2) void fstage_kernel(FArgs a) {
   const int f = tid >> 4;     // block of this FFT
   const int l = tid & 15;     // lane within the FFT
   const int64_t nb = min((int64_t)kFBlk, a.n_blocks - b0);
+  float2 twl[16];             // this lane's inner twiddles W_256^(l k2), the same in every round
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) twl[k2] = tw[(l * k2) & (kFN - 1)];
   for (int pr = 0; pr < kFPairs; ++pr) {
-    // Pass 1: lane n1 = l transforms z[n1 + 16 n2] over n2.
+    // Pass 1: lane n1 = l transforms z[n1 + 16 n2] over n2 (one 16-bit LDS
+    // read gives both inputs of the pair).
     float2 x[16], X[16];
 #pragma unroll
     for (int n2 = 0; n2 < 16; ++n2) {
       const int r = f * kFN + l + 16 * n2;
-      x[n2] = make_float2((float)vin[r][2 * pr], (float)vin[r][2 * pr + 1]);
+      const uint32_t w = *reinterpret_cast<const uint16_t*>(&vin[r][2 * pr]);
+      x[n2] = make_float2((float)(int8_t)(w & 0xFFu), (float)(int8_t)(w >> 8));
     }
     dft16(x, X);
 #pragma unroll
-    for (int k2 = 0; k2 < 16; ++k2) S[f][l * kFSRow + k2] = cmul(X[k2], tw[(l * k2) & (kFN - 1)]);
+    for (int k2 = 0; k2 < 16; ++k2) S[f][l * kFSRow + k2] = cmul(X[k2], twl[k2]);
     __syncthreads();
     // Pass 2: lane k2 = l transforms over n1; output index k = k2 + 16 k1.
 #pragma unroll
@@ -211,10 +222,13 @@ __global__ __launch_bounds__(256, 2) void fstage_kernel(FArgs a) {
 
 hipError_t launch_fstage(const FArgs& a, hipStream_t s) {
   const int64_t n_bg = (a.n_blocks + kFBlk - 1) / kFBlk;
-  const int64_t grid = n_bg * a.n_ig;
-  if (grid <= 0) return hipSuccess;
+  FArgs b = a;
+  b.n_items = n_bg * a.n_ig;
+  if (b.n_items <= 0) return hipSuccess;
+  b.per_xcd = (b.n_items + kNumXcd - 1) / kNumXcd;
+  const int64_t grid = b.per_xcd * kNumXcd;
   if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fstage_kernel, dim3((unsigned)grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(fstage_kernel, dim3((unsigned)grid), dim3(256), 0, s, b);
   return hipGetLastError();
 }
 
