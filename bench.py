@@ -48,10 +48,21 @@ def cpu_baseline(x_dev, n_channels: int) -> dict:
     oracle.xengine_ci8(xs)
     dt = time.perf_counter() - t0
     cmac = n_channels * N_IN * (N_IN + 1) // 2 * N_T
+    # the paper's comparison is one CPU thread: one channel on one thread
+    oracle.set_num_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.xengine_ci8(xs[:1])
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_num_threads(threads)
+    cmac1 = N_IN * (N_IN + 1) // 2 * N_T
     return {"value": cmac / dt / 1e12, "unit": "Tcmac/s", "cores": min(threads, n_channels), "kind": "oracle",
             "sample": f"{n_channels} of 768 channels x all 524800 products x 8000 samples "
                       f"({cmac:.3e} CMAC, {dt:.1f} s, int64 C oracle, OpenMP over channels)",
-            "seconds": dt, "host_threads": threads, "nproc": os.cpu_count()}
+            "seconds": dt, "host_threads": threads, "nproc": os.cpu_count(),
+            "one_thread": {"value": cmac1 / dt1 / 1e12, "unit": "Tcmac/s", "seconds": dt1,
+                           "sample": "1 channel x all 524800 products x 8000 samples on one thread"}}
 
 
 def serving(seconds: float, warm: float, rate: float, seed: int = 5) -> dict:
@@ -405,6 +416,7 @@ def main() -> int:
                                        stream=stream.cuda_stream)
             torch.cuda.synchronize()
         cpu = cpu_baseline(x, args.cpu_channels)
+        cpu["one_thread"]["gpu_int8_over_this"] = (cmac / (ms_per_step / 1e3) / 1e12) / cpu["one_thread"]["value"]
 
     value = cmac / (ms_per_step / 1e3) / 1e12
     line = {
