@@ -478,9 +478,8 @@ __device__ __forceinline__ void mfma_tile_128(const XArgs& a, int8_t* lds, int c
   };
   // Re products first; the -i rotation of A runs on the VALU while they
   // execute, then the Im products: Im V = (-iA) B^T.  Consecutive MFMAs go to
-  // different accumulators.  Diagonal tiles compute every block (the block
-  // time is set by the full wave anyway) and store only j <= i.
-  // SK: a diagonal wave of a diagonal tile skips its strictly upper block (m 0, n 1).
+  // different accumulators.  SK: a diagonal wave of a diagonal tile skips its
+  // strictly upper block (m 0, n 1).
   auto compute = [&](auto sk, const v4i (&af)[2][2], const v4i (&bf)[2][2]) {
     constexpr bool SK = decltype(sk)::value;
     v4i ra[2][2];
@@ -606,6 +605,233 @@ __device__ __forceinline__ void mfma_tile_128(const XArgs& a, int8_t* lds, int c
     }
 }
 
+// int8 variant of mfma_tile_128 on v_mfma_i32_16x16x64_i8: the same staging,
+// pipeline and 64 x 64 wave tile, as 4 x 4 blocks of 16 x 16.  Each fragment
+// read is one contiguous 1 KB of LDS (16 rows x 64 bytes), and the MFMA moves
+// half the accumulator registers per multiply-accumulate of the 32 x 32 x 32
+// form; measured on the MI355X it runs the C3 integration ≈4 % faster (the
+// clock under load rises from ≈1.67 to ≈1.87 GHz).  A diagonal wave skips the
+// 6 strictly upper 16 x 16 blocks of its quarter.
+template <int EK, bool DIAG>
+__device__ __forceinline__ void mfma_tile_128_i8(const XArgs& a, int8_t* lds, int ch, int split, int I, int J) {
+  constexpr int BT = 128;
+  constexpr int PANEL = BT * kMKC;           // bytes per operand per stage
+  constexpr int STAGE = PANEL * (DIAG ? 1 : 2);
+  constexpr int QPW = BT / 16 / 4;           // 1 KB load instructions per operand per wave
+  constexpr int LPW = QPW * (DIAG ? 1 : 2);  // load instructions per wave per stage
+  static_assert(EK == kElemI8, "16 x 16 x 64 tile is the int8 engine");
+
+  const int8_t* __restrict__ xc = static_cast<const int8_t*>(a.x) + (int64_t)ch * a.ch_stride_b;
+  const int64_t k0 = (int64_t)split * a.k_split_bytes;
+  const int64_t k1 = min(a.k_bytes, k0 + a.k_split_bytes);
+  const int n_st = k1 > k0 ? (int)((k1 - k0 + kMKC - 1) / kMKC) : 0;
+  const int64_t last = ((k1 - 1) >> 4) << 4;   // last valid 16-byte chunk start
+  // Stages whose 64 bytes all lie in [k0, k1) and whose offsets fit 32 bits.
+  const int n_fast = a.row_stride_b < (int64_t(1) << 24) ? (int)((k1 - k0) / kMKC) : 0;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // This lane's part of each load instruction: LDS row lrow (of 16), chunk p.
+  const int lrow = lane >> 2, p = lane & 3;
+  const int8_t* gA[QPW];
+  const int8_t* gB[QPW];
+  uint32_t oA[QPW], oB[QPW];
+  int rowq[QPW];
+  const int8_t* tA = xc + (int64_t)(I * BT) * a.row_stride_b + k0;
+  const int8_t* tB = xc + (int64_t)(J * BT) * a.row_stride_b + k0;
+#pragma unroll
+  for (int q = 0; q < QPW; ++q) {
+    const int r = (wave * QPW + q) * 16 + lrow;    // tile row
+    rowq[q] = r;
+    const int c = p ^ swz(r);                      // global chunk this lane fetches
+    const int ra = min(I * BT + r, a.n_in - 1);
+    const int rb = min(J * BT + r, a.n_in - 1);
+    gA[q] = xc + (int64_t)ra * a.row_stride_b + 16 * c;
+    gB[q] = xc + (int64_t)rb * a.row_stride_b + 16 * c;
+    oA[q] = (uint32_t)((int64_t)(ra - I * BT) * a.row_stride_b + 16 * c);
+    oB[q] = (uint32_t)((int64_t)(rb - J * BT) * a.row_stride_b + 16 * c);
+  }
+  auto issue = [&](int st) {
+    int8_t* base = lds + (st % kMNS) * STAGE + wave * QPW * 1024;
+    if (st < n_fast) {
+      const int8_t* ga = tA + st * kMKC;
+      const int8_t* gb = tB + st * kMKC;
+#pragma unroll
+      for (int q = 0; q < QPW; ++q) {
+        __builtin_amdgcn_global_load_lds(ga + oA[q], base + q * 1024, 16, 0, 0);
+        if (!DIAG) __builtin_amdgcn_global_load_lds(gb + oB[q], base + q * 1024 + PANEL, 16, 0, 0);
+      }
+    } else {
+      const int64_t kb = k0 + (int64_t)st * kMKC;
+#pragma unroll
+      for (int q = 0; q < QPW; ++q) {
+        const int c = p ^ swz(rowq[q]);
+        const int64_t kk = kb + 16 * c;
+        const int64_t off = (kk <= last ? kb : last - 16 * c);   // keep the 16 bytes inside the row
+        __builtin_amdgcn_global_load_lds(gA[q] + off, base + q * 1024, 16, 0, 0);
+        if (!DIAG) __builtin_amdgcn_global_load_lds(gB[q] + off, base + q * 1024 + PANEL, 16, 0, 0);
+      }
+    }
+  };
+  // Zero / mask the chunks of stage st that reach past k1 (only the last stage).
+  auto fix_tail = [&](int st) {
+    int8_t* base = lds + (st % kMNS) * STAGE;
+    const int64_t kb = k0 + (int64_t)st * kMKC;
+#pragma unroll
+    for (int q = 0; q < QPW; ++q) {
+      const int c = p ^ swz(rowq[q]);
+      const int64_t kk = kb + 16 * c;
+      if (kk + 16 > k1) {
+        const int64_t valid = k1 - kk;
+#pragma unroll
+        for (int op = 0; op < (DIAG ? 1 : 2); ++op) {
+          v4i* cell = reinterpret_cast<v4i*>(base + op * PANEL + (wave * QPW + q) * 1024 + lane * 16);
+          v4i v = *cell;
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            const int64_t lo = 4 * w;
+            const int keep = valid >= lo + 4 ? 4 : (valid > lo ? (int)(valid - lo) : 0);
+            const uint32_t m = keep >= 4 ? 0xFFFFFFFFu : ((1u << (8 * keep)) - 1u);
+            v[w] = (int)((uint32_t)v[w] & m);
+          }
+          *cell = v;
+        }
+      }
+    }
+  };
+
+  v4i vr[4][4], vi[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      vr[m][n] = v4i{0, 0, 0, 0};
+      vi[m][n] = v4i{0, 0, 0, 0};
+    }
+
+#pragma unroll
+  for (int s = 0; s < kMNS - 1; ++s)
+    if (s < n_st) issue(s);
+
+  const bool tail = (k1 - k0) % kMKC != 0;
+  // Wait for this wave's loads of stage st (later stages stay in flight),
+  // mask the K tail, and make stage st visible to all waves.  A plain
+  // s_barrier: a fenced one would also drain the later stages' loads.
+  auto arrive = [&](int st) {
+    const int ahead = min(kMNS - 2, n_st - 1 - st);
+    if (ahead >= 2) wait_vmcnt<2 * LPW>();
+    else if (ahead == 1) wait_vmcnt<LPW>();
+    else wait_vmcnt<0>();
+    if (tail && st == n_st - 1) fix_tail(st);
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    asm volatile("s_barrier" ::: "memory");
+  };
+  // 16 x 16 x 64 fragments: lane l reads row (l % 16) of a 16-row block,
+  // 16-byte chunk l / 16 (the whole 64-byte stage row across 4 lanes).
+  auto read = [&](int st, v4i (&af)[4], v4i (&bf)[4]) {
+    const int8_t* As = lds + (st % kMNS) * STAGE;
+    const int8_t* Bs = DIAG ? As : As + PANEL;
+    const int c = lane >> 4;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int r = wm * 64 + m * 16 + (lane & 15);
+      af[m] = *reinterpret_cast<const v4i*>(As + r * kMKC + 16 * (c ^ swz(r)));
+    }
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const int r = wn * 64 + n * 16 + (lane & 15);
+      bf[n] = *reinterpret_cast<const v4i*>(Bs + r * kMKC + 16 * (c ^ swz(r)));
+    }
+  };
+  auto compute = [&](auto sk, const v4i (&af)[4], const v4i (&bf)[4]) {
+    constexpr bool SK = decltype(sk)::value;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+        if (!(SK && n > m)) vr[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[m], bf[n], vr[m][n], 0, 0, 0);
+    v4i ra[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) ra[m] = rotm4<kElemI8>(af[m]);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+        if (!(SK && n > m)) vi[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ra[m], bf[n], vi[m][n], 0, 0, 0);
+  };
+
+  if (n_st > 0) {
+    arrive(0);
+    if (kMNS - 1 < n_st) issue(kMNS - 1);
+  }
+  // In a diagonal tile the wave of the strictly upper 64 x 64 quarter only
+  // loads its share of the panel and keeps the barriers.
+  if (DIAG && wm < wn) {
+    for (int s = 0; s + 1 < n_st; ++s) {
+      arrive(s + 1);
+      if (s + kMNS < n_st) issue(s + kMNS);
+    }
+    return;
+  }
+  auto run = [&](auto sk) {
+    constexpr int NM = (DIAG && decltype(sk)::value) ? 20 : 32;   // MFMAs per stage
+    v4i af0[4], bf0[4], af1[4], bf1[4];
+    if (n_st > 0) read(0, af0, bf0);
+    for (int s = 0; s + 1 < n_st; ++s) {
+      arrive(s + 1);
+      if (s + kMNS < n_st) issue(s + kMNS);
+      read(s + 1, af1, bf1);
+      compute(sk, af0, bf0);
+#pragma unroll
+      for (int q = 0; q < (NM < 8 ? NM : 8); ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+      }
+      if constexpr (NM > 8) __builtin_amdgcn_sched_group_barrier(0x008, NM - 8, 0);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        af0[m] = af1[m];
+        bf0[m] = bf1[m];
+      }
+    }
+    if (n_st > 0) compute(sk, af0, bf0);
+  };
+  if (DIAG && wm == wn) run(std::true_type{});
+  else run(std::false_type{});
+
+  // Epilogue.  32 x 32 accumulator layout: register r of lane l holds row
+  // 8*(r/4) + 4*(l/32) + r%4, column l%32.
+  // 16 x 16 accumulator layout: register r of lane l holds row 4*(l/16) + r,
+  // column l%16.
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const int j = J * BT + wn * 64 + n * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = I * BT + wm * 64 + m * 16 + 4 * (lane >> 4) + r;
+        if (i < a.n_in && j <= i) {
+          const int64_t off = (int64_t)split * a.out_split_stride + (int64_t)ch * a.n_products + tri_index(i, j);
+          int2* pp = static_cast<int2*>(a.out) + off;
+          const int re = vr[m][n][r];
+          const int im = (i == j) ? 0 : vi[m][n][r];
+          if (a.accumulate) {
+            int2 o = *pp;
+            o.x += re;
+            o.y += im;
+            *pp = o;
+          } else {
+            *pp = make_int2(re, im);
+          }
+        }
+      }
+    }
+}
+
 template <int EK>
 __global__ __launch_bounds__(256, 2) void xeng_mfma_128_kernel(XArgs a) {
   __shared__ __attribute__((aligned(1024))) int8_t lds[kMNS * 2 * 128 * kMKC];
@@ -618,8 +844,13 @@ __global__ __launch_bounds__(256, 2) void xeng_mfma_128_kernel(XArgs a) {
   const int ch = (int)(rest / a.n_split);
   int I, J;
   tile_decode(tile, I, J);
-  if (I == J) mfma_tile_128<EK, true>(a, lds, ch, split, I, J);
-  else mfma_tile_128<EK, false>(a, lds, ch, split, I, J);
+  if constexpr (EK == kElemI8) {
+    if (I == J) mfma_tile_128_i8<EK, true>(a, lds, ch, split, I, J);
+    else mfma_tile_128_i8<EK, false>(a, lds, ch, split, I, J);
+  } else {
+    if (I == J) mfma_tile_128<EK, true>(a, lds, ch, split, I, J);
+    else mfma_tile_128<EK, false>(a, lds, ch, split, I, J);
+  }
 }
 
 template <int EK, int BT>
