@@ -159,8 +159,8 @@ def serving(seconds: float, warm: float, rate: float, seed: int = 5) -> dict:
 # WRITE_SIZE runs calibrated against a 1 GiB device copy (FETCH x 2.000,
 # WRITE x 1.000); valid only for the kernel source they were taken on.
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_0906_1887_amd", "csrc", "xengine_mfma.hip")
-TRAFFIC_SHA1 = "a546562f74c4f33e2a3c5aeb24d11b8fb0cefdbf"
-TRAFFIC_BYTES = {"read": 2 * 2.9245e7 * 1024, "write": 3.74832e6 * 1024}
+TRAFFIC_SHA1 = "23a931191c000bb22e62b266492daaf60755ee25"
+TRAFFIC_BYTES = {"read": 2 * 2.77692e7 * 1024, "write": 3.38402e6 * 1024}
 
 
 def measured_traffic():
@@ -388,7 +388,7 @@ def main() -> int:
     achieved = ops / (kern_avg / 1e3) / 1e12
     peak = perfmodel.MI355X["int8_ops"] / 1e12
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": measured_traffic(), "kernel": "corr::xeng_mfma_128_kernel<0> (int8, 128x128 tiles, 4 waves of 64x64)",
+            "traffic": measured_traffic(), "kernel": "corr::xeng_mfma_128_kernel<0> (int8 v_mfma_i32_16x16x64_i8, 128x128 tiles, 4 waves of 64x64)",
             "kernel_ms_avg": kern_avg, "kernel_ms_min": kern_ms[0], "kernel_ms_median": kern_ms[len(kern_ms) // 2],
             "algorithmic_bytes": float(N_CH * N_IN * N_T * 2 + N_CH * (N_IN * (N_IN + 1) // 2) * 8)}
 
