@@ -28,7 +28,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int64_t kSplitGranule = 64;  // samples; multiple of every engine's K chunk
 constexpr int kMaxSplit = 16;
-constexpr int kTargetItems = 2048;     // workgroups wanted per X-engine launch
+constexpr int kTargetItems = 1024;     // workgroups wanted per X-engine launch (split-K below this)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
