@@ -98,6 +98,15 @@ __device__ __forceinline__ void dft16(const float2 (&x)[16], float2 (&X)[16]) {
   }
 }
 
+// Orders the LDS accesses of one wave around an exchange among its own lanes:
+// a wave's LDS instructions execute in program order, so only the compiler
+// has to be kept from moving them (no workgroup barrier is needed).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ int8_t requant(float x, float s, float m) {
   float r = rintf(s * x);  // round half to even
   r = fminf(fmaxf(r, -m), m);
@@ -106,7 +115,7 @@ __device__ __forceinline__ int8_t requant(float x, float s, float m) {
 
 __global__ __launch_bounds__(256, 2) void fstage_kernel(FArgs a) {
   __shared__ __attribute__((aligned(16))) int8_t vin[kFBlk * kFN][kFIn];            // 32 KB
-  __shared__ __attribute__((aligned(16))) float2 S[kFFtPerRound][kFSRow * 16];       // 34 KB
+  __shared__ __attribute__((aligned(16))) float2 S[kFFtPerRound][kFSRow * 16];       // 34 KB; slot f: lanes 16f..16f+15 only
   __shared__ __attribute__((aligned(16))) uint16_t O[kFCh][2][kFBlk];                // 8 KB
   __shared__ float2 tw[kFN];
 
@@ -168,15 +177,15 @@ __global__ __launch_bounds__(256, 2) void fstage_kernel(FArgs a) {
     dft16(x, X);
 #pragma unroll
     for (int k2 = 0; k2 < 16; ++k2) S[f][l * kFSRow + k2] = cmul(X[k2], twl[k2]);
-    __syncthreads();
+    wave_sync();
     // Pass 2: lane k2 = l transforms over n1; output index k = k2 + 16 k1.
 #pragma unroll
     for (int n1 = 0; n1 < 16; ++n1) x[n1] = S[f][n1 * kFSRow + l];
     dft16(x, X);
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int k1 = 0; k1 < 16; ++k1) S[f][l + 16 * k1] = X[k1];
-    __syncthreads();
+    wave_sync();
     // Split the two real inputs and requantise channels k < 128.
     const int64_t blk_g = b0 + f;
 #pragma unroll
