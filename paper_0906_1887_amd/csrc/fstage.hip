@@ -21,8 +21,6 @@ namespace corr {
 constexpr int kFN = 256;          // FFT length
 constexpr int kFCh = kFN / 2;     // channels kept
 constexpr int kFBlk = 16;         // blocks per workgroup
-constexpr int kFIn = 8;           // inputs per workgroup (4 pairs)
-constexpr int kFPairs = kFIn / 2;
 constexpr int kFFtPerRound = 16;  // 256 threads / 16 lanes per FFT
 constexpr int kFSRow = 17;        // padded row of the 16x16 exchange
 
@@ -35,10 +33,10 @@ struct FArgs {
   int64_t ring_stride;     // samples per ring row
   int64_t t_offset;        // ring time index of block 0
   int32_t n_in;
-  int32_t n_ig;            // input groups = ceil(n_in / 8)
+  int32_t n_ig;            // input groups = ceil(n_in / inputs per workgroup)
   float scale;             // requantisation scale s
   float max_abs;
-  int32_t vec_in;          // 1: n_in % 8 == 0 and volt 8-byte aligned
+  int32_t vec_in;          // 1: n_in a multiple of, and volt aligned to, the inputs per workgroup
   int32_t vec_out;         // 1: t_offset % 8 == 0 and ring_stride % 8 == 0
   int64_t n_items;         // block groups x input groups
   int64_t per_xcd;         // ceil(n_items / 8)
@@ -107,17 +105,46 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ int8_t requant(float x, float s, float m) {
-  float r = rintf(s * x);  // round half to even
-  r = fminf(fmaxf(r, -m), m);
-  return (int8_t)(int)r;
+// Requantisation q = clip(rne(h * v), +-m) in two instructions: adding
+// 1.5 * 2^23 rounds h * v (exactly formed inside the FMA) to an integer with
+// the FPU's round-half-to-even, and the clamp happens in that offset
+// domain, where [M - m, M + m] is exact.  The low byte of the result's bit
+// pattern is then q as a two's-complement int8 (the pattern is
+// 0x4B400000 + q for |q| < 2^22; larger values are clamped first).
+constexpr float kRqMagic = 12582912.0f;  // 1.5 * 2^23
+__device__ __forceinline__ uint32_t requant_bits(float v, float h, float lo, float hi) {
+  return __float_as_uint(__builtin_amdgcn_fmed3f(fmaf(v, h, kRqMagic), lo, hi));
 }
 
-__global__ __launch_bounds__(256, 2) void fstage_kernel(FArgs a) {
-  __shared__ __attribute__((aligned(16))) int8_t vin[kFBlk * kFN][kFIn];            // 32 KB
-  __shared__ __attribute__((aligned(16))) float2 S[kFFtPerRound][kFSRow * 16];       // 34 KB; slot f: lanes 16f..16f+15 only
-  __shared__ __attribute__((aligned(16))) uint16_t O[kFCh][2][kFBlk];                // 8 KB
-  __shared__ float2 tw[kFN];
+// Low bytes of four requantised values -> (b0, b1, b2, b3) of one word.
+__device__ __forceinline__ uint32_t pack4(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3) {
+  const uint32_t lo = __builtin_amdgcn_perm(b1, b0, 0x0c0c0400u);  // (b0.0, b1.0, 0, 0)
+  const uint32_t hi = __builtin_amdgcn_perm(b3, b2, 0x04000c0cu);  // (0, 0, b2.0, b3.0)
+  return lo | hi;
+}
+
+// Signed byte j of w as float.
+template <int J>
+__device__ __forceinline__ float sbyte(uint32_t w) {
+  return (float)((int32_t)(w << (24 - 8 * J)) >> 24);
+}
+
+// One workgroup: 16 consecutive blocks x IN inputs (IN = 8 or 16, IN / 2
+// pairs).  FFT slot f = tid / 16 (lanes l = tid % 16) owns block f: it loads
+// its 16 samples x IN inputs straight into registers (IN bytes of each
+// n_in-byte time row; more inputs per workgroup means fewer, fuller cache
+// line requests) and runs one 256-point FFT per pair.  The exchange buffer
+// S[f] is used by the 16 lanes of slot f only, all in one wave; O is the
+// workgroup's corner turn for the current pair.
+constexpr int kORow = 20;  // words per channel row of O (16 blocks + pad, 16-byte aligned rows)
+
+template <int IN>
+__global__ __launch_bounds__(256, 3) void fstage_kernel(FArgs a) {
+  static_assert(IN == 8 || IN == 16, "inputs per workgroup");
+  constexpr int kW = IN / 4;  // words per sample and lane
+  __shared__ __attribute__((aligned(16))) float2 S[kFFtPerRound][kFSRow * 16];  // 34 KB
+  __shared__ __attribute__((aligned(16))) uint32_t O[kFCh][kORow];              // 10 KB
+  __shared__ float2 tw[kFN];                                                     // 2 KB
 
   const int tid = threadIdx.x;
   // The n_ig workgroups of one block group read the same input rows; the
@@ -126,118 +153,162 @@ __global__ __launch_bounds__(256, 2) void fstage_kernel(FArgs a) {
   if ((int64_t)(blockIdx.x / kNumXcd) >= a.per_xcd || item >= a.n_items) return;
   const int ig = (int)(item % a.n_ig);
   const int64_t b0 = (item / a.n_ig) * kFBlk;
-  const int i0 = ig * kFIn;
-
-  tw[tid] = a.twiddle[tid];
-
-  // Load [16 blocks * 256 samples][8 inputs] (zero outside): all 16 loads of
-  // a thread are in flight before the first LDS write.
-  constexpr int kLoads = kFBlk * kFN / 256;
-  if (a.vec_in && b0 + kFBlk <= a.n_blocks) {
-    uint2 w[kLoads];
-    const int8_t* p = a.volt + (b0 * kFN + tid) * a.n_in + i0;
-#pragma unroll
-    for (int q = 0; q < kLoads; ++q) w[q] = *reinterpret_cast<const uint2*>(p + (int64_t)q * 256 * a.n_in);
-#pragma unroll
-    for (int q = 0; q < kLoads; ++q) *reinterpret_cast<uint2*>(&vin[tid + 256 * q][0]) = w[q];
-  } else {
-    for (int r = tid; r < kFBlk * kFN; r += 256) {
-      const int64_t t = b0 * kFN + r;
-      uint8_t bytes[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (t < a.n_blocks * kFN) {
-        const int8_t* p = a.volt + t * a.n_in + i0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) bytes[q] = (i0 + q < a.n_in) ? (uint8_t)p[q] : 0u;
-      }
-      uint2 w;
-      w.x = bytes[0] | (bytes[1] << 8) | (bytes[2] << 16) | ((uint32_t)bytes[3] << 24);
-      w.y = bytes[4] | (bytes[5] << 8) | (bytes[6] << 16) | ((uint32_t)bytes[7] << 24);
-      *reinterpret_cast<uint2*>(&vin[r][0]) = w;
-    }
-  }
-  __syncthreads();
-
-  // One round per input pair: FFT slot f transforms block f of the pair.
-  const int f = tid >> 4;     // block of this FFT
-  const int l = tid & 15;     // lane within the FFT
+  const int i0 = ig * IN;
+  const int f = tid >> 4;  // block of this FFT slot
+  const int l = tid & 15;  // lane within the FFT
   const int64_t nb = min((int64_t)kFBlk, a.n_blocks - b0);
-  float2 twl[16];             // this lane's inner twiddles W_256^(l k2), the same in every round
-#pragma unroll
-  for (int k2 = 0; k2 < 16; ++k2) twl[k2] = tw[(l * k2) & (kFN - 1)];
-  for (int pr = 0; pr < kFPairs; ++pr) {
-    // Pass 1: lane n1 = l transforms z[n1 + 16 n2] over n2 (one 16-bit LDS
-    // read gives both inputs of the pair).
-    float2 x[16], X[16];
+
+  // Samples t = l + 16 n2 of block b0 + f, inputs i0..i0+IN-1 (zero outside).
+  uint32_t w[16][kW];
+  if (a.vec_in && nb == kFBlk) {
+    const int8_t* p = a.volt + ((b0 + f) * kFN + l) * a.n_in + i0;
 #pragma unroll
     for (int n2 = 0; n2 < 16; ++n2) {
-      const int r = f * kFN + l + 16 * n2;
-      const uint32_t w = *reinterpret_cast<const uint16_t*>(&vin[r][2 * pr]);
-      x[n2] = make_float2((float)(int8_t)(w & 0xFFu), (float)(int8_t)(w >> 8));
-    }
-    dft16(x, X);
-#pragma unroll
-    for (int k2 = 0; k2 < 16; ++k2) S[f][l * kFSRow + k2] = cmul(X[k2], twl[k2]);
-    wave_sync();
-    // Pass 2: lane k2 = l transforms over n1; output index k = k2 + 16 k1.
-#pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) x[n1] = S[f][n1 * kFSRow + l];
-    dft16(x, X);
-    wave_sync();
-#pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) S[f][l + 16 * k1] = X[k1];
-    wave_sync();
-    // Split the two real inputs and requantise channels k < 128.
-    const int64_t blk_g = b0 + f;
-#pragma unroll
-    for (int k1 = 0; k1 < 8; ++k1) {
-      const int k = l + 16 * k1;
-      const float2 zk = X[k1];
-      const float2 zm = S[f][(kFN - k) & (kFN - 1)];
-      const float2 xa = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-      const float2 xb = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
-      O[k][0][f] = (uint16_t)(uint8_t)requant(xa.x, a.scale, a.max_abs) |
-                   ((uint16_t)(uint8_t)requant(xa.y, a.scale, a.max_abs) << 8);
-      O[k][1][f] = (uint16_t)(uint8_t)requant(xb.x, a.scale, a.max_abs) |
-                   ((uint16_t)(uint8_t)requant(xb.y, a.scale, a.max_abs) << 8);
-      if (a.dbg != nullptr && blk_g < a.n_blocks) {
-        const int ia = i0 + 2 * pr, ib = ia + 1;
-        if (ia < a.n_in)
-          reinterpret_cast<float2*>(a.dbg)[((int64_t)k * a.n_in + ia) * a.n_blocks + blk_g] = xa;
-        if (ib < a.n_in)
-          reinterpret_cast<float2*>(a.dbg)[((int64_t)k * a.n_in + ib) * a.n_blocks + blk_g] = xb;
+      const int8_t* q = p + (int64_t)n2 * 16 * a.n_in;
+      if constexpr (IN == 16) {
+        const uint4 v = *reinterpret_cast<const uint4*>(q);
+        w[n2][0] = v.x; w[n2][1] = v.y; w[n2][2] = v.z; w[n2][3] = v.w;
+      } else {
+        const uint2 v = *reinterpret_cast<const uint2*>(q);
+        w[n2][0] = v.x; w[n2][1] = v.y;
       }
     }
-    __syncthreads();
-    // Write O[k][2 inputs][16 blocks] to ring[k][input][t_offset + b0 ..]:
-    // one 32-byte row segment per thread.
-    {
-      const int k = tid >> 1, il = tid & 1;
-      const int i = i0 + 2 * pr + il;
-      if (i < a.n_in) {
-        uint16_t* dst =
-            reinterpret_cast<uint16_t*>(a.ring) + ((int64_t)k * a.n_in + i) * a.ring_stride + a.t_offset + b0;
-        if (a.vec_out && nb == kFBlk) {
-          const uint4* src = reinterpret_cast<const uint4*>(&O[k][il][0]);
-          reinterpret_cast<uint4*>(dst)[0] = src[0];
-          reinterpret_cast<uint4*>(dst)[1] = src[1];
-        } else {
-          for (int q = 0; q < nb; ++q) dst[q] = O[k][il][q];
+  } else {
+#pragma unroll
+    for (int n2 = 0; n2 < 16; ++n2) {
+      const int64_t t = (b0 + f) * kFN + l + 16 * n2;
+      const int8_t* p = a.volt + t * a.n_in + i0;
+#pragma unroll
+      for (int j = 0; j < kW; ++j) {
+        uint32_t v = 0;
+        for (int q = 0; q < 4; ++q) {
+          const int i = 4 * j + q;
+          if (f < nb && i0 + i < a.n_in) v |= (uint32_t)(uint8_t)p[i] << (8 * q);
+        }
+        w[n2][j] = v;
+      }
+    }
+  }
+  // Twiddle table W_256^m; a lane reads W_256^(l k2) for every round from it
+  // (the first round's barrier orders these writes before the first read).
+  tw[tid] = a.twiddle[tid];
+
+  const float h = 0.5f * a.scale;  // the 1/2 of the two-for-one split folded into the scale
+  const float lo = kRqMagic - a.max_abs, hi = kRqMagic + a.max_abs;
+  // Mirror lookup: Z_{256-k} for k = l + 16 k1 sits in lane (16 - l) % 16 at
+  // index 15 - k1 (l > 0) or in lane 0 at index 16 - k1 (l = 0, k1 > 0); the
+  // second half X[8..15] of every lane is parked at S[f][lane + 16 (idx - 8)].
+  const int mbase = ((16 - l) & 15) + 16 * 7 + (l == 0 ? 16 : 0);
+
+  // Groups of 4 pairs (8 inputs, two words per sample); after a group the
+  // next two words move down so that every round reads w[.][0..1].
+#pragma unroll 1
+  for (int g = 0; g < IN / 8; ++g) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int pr = 4 * g + r;
+      // Pass 1: lane n1 = l transforms z[n1 + 16 n2] over n2, z = a + i b.
+      float2 x[16], X[16];
+#pragma unroll
+      for (int n2 = 0; n2 < 16; ++n2) {
+        const uint32_t d = w[n2][r >> 1];
+        if (r & 1)
+          x[n2] = make_float2(sbyte<2>(d), sbyte<3>(d));
+        else
+          x[n2] = make_float2(sbyte<0>(d), sbyte<1>(d));
+      }
+      dft16(x, X);
+      if (pr == 0) __syncthreads();  // tw is complete
+      S[f][l * kFSRow] = X[0];
+#pragma unroll
+      for (int k2 = 1; k2 < 16; ++k2) S[f][l * kFSRow + k2] = cmul(X[k2], tw[(l * k2) & (kFN - 1)]);
+      wave_sync();
+      // Pass 2: lane k2 = l transforms over n1; output index k = k2 + 16 k1.
+#pragma unroll
+      for (int n1 = 0; n1 < 16; ++n1) x[n1] = S[f][n1 * kFSRow + l];
+      dft16(x, X);
+      wave_sync();
+#pragma unroll
+      for (int k1 = 8; k1 < 16; ++k1) S[f][l + 16 * (k1 - 8)] = X[k1];
+      wave_sync();
+      // Split the two real inputs (X_a = (Z_k + conj Z_{N-k})/2,
+      // X_b = (Z_k - conj Z_{N-k})/(2i)) and requantise channels k < 128.
+      const int64_t blk_g = b0 + f;
+#pragma unroll
+      for (int k1 = 0; k1 < 8; ++k1) {
+        const int k = l + 16 * k1;
+        const float2 zk = X[k1];
+        float2 zm = S[f][mbase - 16 * k1];
+        if (k1 == 0 && l == 0) zm = X[0];
+        const float ar = zk.x + zm.x, ai = zk.y - zm.y;
+        const float br = zk.y + zm.y, bi = zm.x - zk.x;
+        O[k][f] = pack4(requant_bits(ar, h, lo, hi), requant_bits(ai, h, lo, hi), requant_bits(br, h, lo, hi),
+                        requant_bits(bi, h, lo, hi));
+        if (a.dbg != nullptr && blk_g < a.n_blocks) {
+          const int ia = i0 + 2 * pr, ib = ia + 1;
+          if (ia < a.n_in)
+            reinterpret_cast<float2*>(a.dbg)[((int64_t)k * a.n_in + ia) * a.n_blocks + blk_g] =
+                make_float2(0.5f * ar, 0.5f * ai);
+          if (ib < a.n_in)
+            reinterpret_cast<float2*>(a.dbg)[((int64_t)k * a.n_in + ib) * a.n_blocks + blk_g] =
+                make_float2(0.5f * br, 0.5f * bi);
         }
       }
+      __syncthreads();
+      // Write the pair's rows ring[k][input][t_offset + b0 ..] (32 bytes
+      // each) as 16-byte pieces: piece p = tid + 256 j is half p & 1 of row
+      // p >> 1 = (k, il), so two neighbouring lanes fill one row.  A piece
+      // holds the il-th 16-bit half of O[k][8 half .. 8 half + 7].
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int pc = tid + 256 * j;
+        const int hf = pc & 1, row = pc >> 1;
+        const int k = row >> 1, il = row & 1;
+        const int i = i0 + 2 * pr + il;
+        if (i < a.n_in) {
+          uint16_t* dst = reinterpret_cast<uint16_t*>(a.ring) + ((int64_t)k * a.n_in + i) * a.ring_stride +
+                          a.t_offset + b0 + 8 * hf;
+          const uint4* src = reinterpret_cast<const uint4*>(&O[k][8 * hf]);
+          const uint4 q0 = src[0], q1 = src[1];
+          const uint32_t sel = il ? 0x07060302u : 0x05040100u;
+          const uint4 o = make_uint4(__builtin_amdgcn_perm(q0.y, q0.x, sel), __builtin_amdgcn_perm(q0.w, q0.z, sel),
+                                     __builtin_amdgcn_perm(q1.y, q1.x, sel), __builtin_amdgcn_perm(q1.w, q1.z, sel));
+          if (a.vec_out && nb == kFBlk) {
+            *reinterpret_cast<uint4*>(dst) = o;
+          } else {
+            const uint32_t v[4] = {o.x, o.y, o.z, o.w};
+            for (int q = 0; q < 8 && 8 * hf + q < nb; ++q) dst[q] = (uint16_t)(v[q >> 1] >> (16 * (q & 1)));
+          }
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
+    if constexpr (IN == 16) {
+#pragma unroll
+      for (int n2 = 0; n2 < 16; ++n2) {
+        w[n2][0] = w[n2][2];
+        w[n2][1] = w[n2][3];
+      }
+    }
   }
 }
 
+// 16 inputs per workgroup when n_in is a multiple of 16, else 8.
 hipError_t launch_fstage(const FArgs& a, hipStream_t s) {
+  const int in = (a.n_in % 16 == 0) ? 16 : 8;
   const int64_t n_bg = (a.n_blocks + kFBlk - 1) / kFBlk;
   FArgs b = a;
-  b.n_items = n_bg * a.n_ig;
+  b.n_ig = (a.n_in + in - 1) / in;
+  b.vec_in = (a.n_in % in == 0) && ((reinterpret_cast<uintptr_t>(a.volt) & (in - 1)) == 0);
+  b.n_items = n_bg * b.n_ig;
   if (b.n_items <= 0) return hipSuccess;
   b.per_xcd = (b.n_items + kNumXcd - 1) / kNumXcd;
   const int64_t grid = b.per_xcd * kNumXcd;
   if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fstage_kernel, dim3((unsigned)grid), dim3(256), 0, s, b);
+  if (in == 16)
+    hipLaunchKernelGGL(fstage_kernel<16>, dim3((unsigned)grid), dim3(256), 0, s, b);
+  else
+    hipLaunchKernelGGL(fstage_kernel<8>, dim3((unsigned)grid), dim3(256), 0, s, b);
   return hipGetLastError();
 }
 
@@ -255,10 +326,8 @@ hipError_t launch_fstage_call(const FStageCall& c, hipStream_t s) {
   a.ring_stride = c.ring_stride;
   a.t_offset = c.t_offset;
   a.n_in = c.n_in;
-  a.n_ig = (c.n_in + kFIn - 1) / kFIn;
   a.scale = c.scale;
   a.max_abs = c.max_abs;
-  a.vec_in = (c.n_in % kFIn == 0) && ((reinterpret_cast<uintptr_t>(c.volt) & 7) == 0);
   a.vec_out = (c.t_offset % 8 == 0) && (c.ring_stride % 8 == 0) && ((reinterpret_cast<uintptr_t>(c.ring) & 15) == 0);
   return launch_fstage(a, s);
 }

@@ -51,7 +51,8 @@ def check_spectra_and_requant(v, dbg, q_gpu, n_in):
 
 
 def test_fstage_small_and_x_on_gpu_spectra():
-    for n_in, nb_list in ((64, [64]), (13, [37, 20]), (8, [16, 1, 15])):
+    # 16 inputs per workgroup: 64, 48 (ragged block groups); 8: 24, 8; bytewise: 13
+    for n_in, nb_list in ((64, [64]), (48, [16, 23]), (24, [40]), (13, [37, 20]), (8, [16, 1, 15])):
         say(f"[fstage] n_in={n_in} blocks={nb_list}")
         c = fx(n_in, ring=sum(nb_list) + 5)
         seq = 100
