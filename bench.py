@@ -187,10 +187,17 @@ def other_configs(dev, stream):
     """C1, C2 and C4 at their full sizes: one timed figure per step of the
     path, against its roofline (inputs made on the device; timing only, the
     parity of these configurations is checked by the GPU tests)."""
+    out = {}
+    out.update(c1_config(dev, stream))
+    out.update(c2_config(dev, stream))
+    out.update(c4_config(dev, stream))
+    return out
+
+
+def c1_config(dev, stream):
     import torch
     import synth
     from paper_0906_1887_amd import Correlator, perfmodel
-    hbm = perfmodel.MI355X["hbm_Bps"]
     out = {}
 
     # C1: plain FP32 X-engine, N_I=64, 128 channels, 1000 samples, complex float32
@@ -211,6 +218,14 @@ def other_configs(dev, stream):
                             "note": "X + accumulator reset per integration, 200 back-to-back"}
     c.close()
     del x8, xf
+    return out
+
+
+def c2_config(dev, stream, reps=20):
+    import torch
+    from paper_0906_1887_amd import Correlator, perfmodel
+    hbm = perfmodel.MI355X["hbm_Bps"]
+    out = {}
 
     # C2: F-stage (256-pt real FFT, requantise, corner turn) and X on the ring, N_I=64
     n_in, nb = 64, 10000
@@ -228,7 +243,6 @@ def other_configs(dev, stream):
         c.correlate(None)
         c.dump(0)
     f()
-    reps = 20
     e = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
           torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
     torch.cuda.synchronize()
@@ -255,6 +269,14 @@ def other_configs(dev, stream):
                             "per sample, X 2 B per sample in + 8 B per product out"}
     c.close()
     del volt
+    return out
+
+
+def c4_config(dev, stream):
+    import torch
+    from paper_0906_1887_amd import Correlator, perfmodel
+    hbm = perfmodel.MI355X["hbm_Bps"]
+    out = {}
 
     # C4: FP16 / FP8 staging + matrix-core X-engine, N_I=256, 1024 channels, 4096 samples
     n_in, n_ch, T = 256, 1024, 4096
@@ -291,9 +313,10 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-other-configs", action="store_true")
-    ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
+    ap.add_argument("--mode", choices=["bench", "copy", "c2"], default="bench",
                     help="copy: only a 1 GiB device-to-device copy, the known-size reference for "
-                         "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
+                         "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE counters; c2: only the C2 "
+                         "F-stage + X-engine timing (for profiling the F-stage)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -317,6 +340,9 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+    if args.mode == "c2":
+        print(json.dumps({"mode": "c2", **c2_config(dev, stream, reps=args.steps)}))
+        return 0
     log("generating input on device")
     x = torch.empty((N_CH, N_IN, N_T, 2), dtype=torch.int8, device=dev)
     synth.DeviceGen().fill_ci8(x.data_ptr(), N_CH, N_IN, N_T, SEED, stream=stream.cuda_stream)

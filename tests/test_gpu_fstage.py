@@ -77,6 +77,22 @@ def test_fstage_small_and_x_on_gpu_spectra():
         c.close()
 
 
+def test_fstage_wide_launches_every_block():
+    """Launches of several waves of 16-input workgroups (1591 blocks: 400
+    items, 3189 blocks: 800 items; both end in a ragged block group), every
+    block's spectra and requantised codes checked."""
+    n_in = 64
+    for nb in (1591, 3189):
+        say(f"[fstage] wide launch n_in={n_in} blocks={nb}")
+        c = fx(n_in, ring=nb + 3)
+        v = synth.real_voltages(seed=5, index=nb, n_blocks=nb, n_inputs=n_in)
+        dbg = torch.empty((128, n_in, nb, 2), dtype=torch.float32, device=DEV)
+        c.channelise(torch.from_numpy(v).to(DEV), first_seq=0, spectra_dbg=dbg)
+        q = c.ring_read().numpy()
+        check_spectra_and_requant(v, dbg.cpu().numpy(), q[:, :, :nb], n_in)
+        c.close()
+
+
 def test_sequence_and_ring_errors():
     c = fx(8, ring=40)
     v = torch.from_numpy(synth.real_voltages(seed=2, index=0, n_blocks=16, n_inputs=8)).to(DEV)
