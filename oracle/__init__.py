@@ -48,6 +48,11 @@ def _load():
         lib.oracle_xengine_pairs_ci8.argtypes = [P, I64, I64, P, P, I64, P]
         lib.oracle_dft_real.argtypes = [P, I64, I64, I64, I64, P]
         lib.oracle_requant.argtypes = [P, I64, ctypes.c_double, ctypes.c_int32, P]
+        lib.oracle_dft_complex.argtypes = [P, I64, I64, I64, P]
+        lib.oracle_unpack_w16.argtypes = [P, I64, P]
+        lib.oracle_unpack_b8.argtypes = [P, I64, P]
+        lib.oracle_aggregate_w16.argtypes = [P, I64, I64, I64, ctypes.c_uint32, P]
+        lib.oracle_aggregate_w16.restype = I64
         lib.oracle_f16_encode.argtypes = [P, I64, P]
         lib.oracle_f16_decode.argtypes = [P, I64, P]
         lib.oracle_e4m3_encode.argtypes = [P, I64, P]
@@ -136,6 +141,48 @@ def dft_real(v: np.ndarray, N: int, n_keep: int | None = None) -> np.ndarray:
     if X.size:
         _load().oracle_dft_real(_ptr(v), N, n_in, nb, n_keep, _ptr(X))
     return X
+
+
+def dft_complex(x: np.ndarray, N: int) -> np.ndarray:
+    """x: int8 [n_blocks*N][n_in][2] complex, time-major -> FP64 [N][n_in][n_blocks][2]."""
+    x = np.ascontiguousarray(x, dtype=np.int8)
+    ns, n_in, two = x.shape
+    assert two == 2 and ns % N == 0
+    nb = ns // N
+    X = np.zeros((N, n_in, nb, 2), dtype=np.float64)
+    if X.size:
+        _load().oracle_dft_complex(_ptr(x), N, n_in, nb, _ptr(X))
+    return X
+
+
+def unpack_w16(w) -> np.ndarray:
+    """uint16 words (5-bit re in bits 9..5, 5-bit im in bits 4..0) -> int8 [..., 2]."""
+    w = np.ascontiguousarray(w, dtype=np.uint16)
+    out = np.zeros(w.shape + (2,), dtype=np.int8)
+    if w.size:
+        _load().oracle_unpack_w16(_ptr(w), w.size, _ptr(out))
+    return out
+
+
+def unpack_b8(b) -> np.ndarray:
+    """uint8 bytes (4-bit re in bits 7..4, 4-bit im in bits 3..0) -> int8 [..., 2]."""
+    b = np.ascontiguousarray(b, dtype=np.uint8)
+    out = np.zeros(b.shape + (2,), dtype=np.int8)
+    if b.size:
+        _load().oracle_unpack_b8(_ptr(b), b.size, _ptr(out))
+    return out
+
+
+def aggregate_w16(rec: np.ndarray, first_counter: int = 0):
+    """rec: uint16 [n_streams][n_rec][1 + w_per] -> (uint16 [n_rec][n_streams * w_per], number
+    of records whose marker/counter word is not first_counter + r (mod 2^16) in some stream)."""
+    rec = np.ascontiguousarray(rec, dtype=np.uint16)
+    ns, nr, wp1 = rec.shape
+    out = np.zeros((nr, ns * (wp1 - 1)), dtype=np.uint16)
+    bad = 0
+    if rec.size:
+        bad = int(_load().oracle_aggregate_w16(_ptr(rec), ns, wp1 - 1, nr, int(first_counter) & 0xFFFF, _ptr(out)))
+    return out, bad
 
 
 def requant(y: np.ndarray, s: float, max_abs: int = 7) -> np.ndarray:

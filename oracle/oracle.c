@@ -26,6 +26,23 @@
  *   oracle_requant
  *       Requantiser of the F-stage output (not in the paper, which correlates
  *       floats): q = clip(round_half_even(s*y), -max_abs, max_abs).
+ *   oracle_unpack_w16 / oracle_unpack_b8
+ *       Sec. 3: a recorded sample has 5-bit real and 5-bit imaginary parts in
+ *       two's complement, stored in a 16-bit word; Sec. 5's "1-byte" mode
+ *       keeps one bit less of each part in a single byte.  The bit positions
+ *       are not stated; read here as re = bits 9..5, im = bits 4..0 (upper
+ *       six bits ignored) and re = bits 7..4, im = bits 3..0.
+ *   oracle_aggregate_w16
+ *       Sec. 3: each capture stream is a run of records of one marker/counter
+ *       word followed by one word per receiver input; the aggregator drops
+ *       the marker words and interleaves the streams so that all inputs of
+ *       one time instant are adjacent.  The marker is read here as a 16-bit
+ *       record counter; records whose counter differs from the expected one
+ *       in any stream are counted.
+ *   oracle_dft_complex
+ *       Sec. 2 / Sec. 4: complex samples, N samples give N channels.  Direct
+ *       DFT in FP64, X_k = sum_n x_n exp(-2 pi i ((k n) mod N) / N) for every
+ *       k < N, natural order (DC first), unnormalised, no window.
  *   oracle_f16_* / oracle_e4m3_*
  *       IEEE binary16 and OCP FP8 E4M3FN codecs with round-half-even (E4M3:
  *       bias 7, no infinities, saturating at 448), written from the formats'
@@ -164,6 +181,91 @@ void oracle_dft_real(const int8_t *v, int64_t N, int64_t n_in, int64_t n_blocks,
     }
     free(cs);
     free(sn);
+}
+
+/* v: int8 [n_blocks*N][n_in][2] complex (re, im), time-major, input fastest.
+ * X: double [N][n_in][n_blocks][2], X[k][i][b] = DFT_k of block b of input i. */
+void oracle_dft_complex(const int8_t *v, int64_t N, int64_t n_in, int64_t n_blocks, double *X)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    if (N <= 0) return;
+    double *cs = (double *)malloc((size_t)N * sizeof(double));
+    double *sn = (double *)malloc((size_t)N * sizeof(double));
+    if (!cs || !sn) { free(cs); free(sn); return; }
+    for (int64_t m = 0; m < N; ++m) {
+        cs[m] = cos(two_pi * (double)m / (double)N);
+        sn[m] = sin(two_pi * (double)m / (double)N);
+    }
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (i = 0; i < n_in; ++i) {
+        for (int64_t b = 0; b < n_blocks; ++b) {
+            for (int64_t k = 0; k < N; ++k) {
+                double re = 0.0, im = 0.0;
+                for (int64_t n = 0; n < N; ++n) {
+                    const int8_t *x = v + ((b * N + n) * n_in + i) * 2;
+                    const double xr = (double)x[0], xi = (double)x[1];
+                    const int64_t m = (k * n) % N;
+                    /* (xr + i xi)(cos - i sin) */
+                    re += xr * cs[m] + xi * sn[m];
+                    im += xi * cs[m] - xr * sn[m];
+                }
+                double *dst = X + ((k * n_in + i) * n_blocks + b) * 2;
+                dst[0] = re;
+                dst[1] = im;
+            }
+        }
+    }
+    free(cs);
+    free(sn);
+}
+
+/* ---------------------------------------------------------- sample formats */
+
+/* Two's-complement value of the low `bits` bits of u. */
+static int32_t sext(uint32_t u, int bits)
+{
+    const uint32_t m = (1u << bits) - 1u;
+    const uint32_t v = u & m;
+    return (v & (1u << (bits - 1))) ? (int32_t)v - (int32_t)(1u << bits) : (int32_t)v;
+}
+
+/* w: uint16 [n]; out: int8 [n][2] (re, im). */
+void oracle_unpack_w16(const uint16_t *w, int64_t n, int8_t *out)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        out[2 * k] = (int8_t)sext((uint32_t)w[k] >> 5, 5);
+        out[2 * k + 1] = (int8_t)sext((uint32_t)w[k], 5);
+    }
+}
+
+/* b: uint8 [n]; out: int8 [n][2] (re, im). */
+void oracle_unpack_b8(const uint8_t *b, int64_t n, int8_t *out)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        out[2 * k] = (int8_t)sext((uint32_t)b[k] >> 4, 4);
+        out[2 * k + 1] = (int8_t)sext((uint32_t)b[k], 4);
+    }
+}
+
+/* rec: uint16 [n_streams][n_rec][1 + w_per]; out: uint16 [n_rec][n_streams * w_per],
+ * out[r][s * w_per + w] = rec[s][r][1 + w].  Returns the number of records r
+ * for which some stream's word 0 differs from (first_counter + r) mod 2^16. */
+int64_t oracle_aggregate_w16(const uint16_t *rec, int64_t n_streams, int64_t w_per, int64_t n_rec,
+                             uint32_t first_counter, uint16_t *out)
+{
+    int64_t bad = 0;
+    for (int64_t r = 0; r < n_rec; ++r) {
+        int mismatch = 0;
+        const uint16_t want = (uint16_t)((first_counter + (uint64_t)r) & 0xFFFFu);
+        for (int64_t s = 0; s < n_streams; ++s) {
+            const uint16_t *src = rec + (s * n_rec + r) * (1 + w_per);
+            if (src[0] != want) mismatch = 1;
+            for (int64_t w = 0; w < w_per; ++w) out[r * n_streams * w_per + s * w_per + w] = src[1 + w];
+        }
+        bad += mismatch;
+    }
+    return bad;
 }
 
 /* ------------------------------------------------------------ requantiser */
