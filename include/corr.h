@@ -79,12 +79,30 @@ typedef enum {
                                  return CORR_E_UNSUPPORTED.                */
 } corr_engine_t;
 
+/* F-stage input formats (corr_config.volt_format). */
+typedef enum {
+    CORR_VOLT_R8 = 0,         /* real int8 samples, 1 byte; real DFT of
+                                 fft_size = 2*n_channels (Sec. 2, Sec. 4)    */
+    CORR_VOLT_CW16 = 1,       /* complex, 5-bit re and 5-bit im in two's
+                                 complement in a 16-bit word, re = bits 9..5,
+                                 im = bits 4..0, bits 15..10 ignored (the
+                                 recorded format of Sec. 3; bit positions are
+                                 this library's reading); complex DFT of
+                                 fft_size = n_channels                       */
+    CORR_VOLT_CB8 = 2         /* complex "1-byte" mode (Sec. 5): 4-bit re in
+                                 bits 7..4, 4-bit im in bits 3..0, two's
+                                 complement; complex DFT of fft_size =
+                                 n_channels                                  */
+} corr_volt_t;
+
 typedef struct {
     int32_t n_inputs;         /* N_I >= 1                                   */
     int32_t n_channels;       /* N_C >= 1                                   */
-    int32_t fft_size;         /* 0: X-engine only.  Else the real FFT length,
-                                 which must equal 2*n_channels (F-stage on;
-                                 this build implements 256)                  */
+    int32_t fft_size;         /* 0: X-engine only.  Else the F-stage's DFT
+                                 length: 2*n_channels for real input (this
+                                 build implements 256), n_channels for
+                                 complex input (this build implements 128);
+                                 other lengths return CORR_E_UNSUPPORTED     */
     int32_t sample_type;      /* corr_sample_t of corr_correlate's input     */
     int32_t engine;           /* corr_engine_t                               */
     int32_t max_abs;          /* > 0: samples are integers with |re|,|im| <=
@@ -96,6 +114,9 @@ typedef struct {
     int64_t ring_samples;     /* F-stage: ring capacity in time samples per
                                  channel (one sample per FFT block).
                                  F16/F8: conversion chunk in samples.        */
+    int32_t volt_format;      /* corr_volt_t of corr_channelise's input (0
+                                 when fft_size is 0)                         */
+    int32_t reserved;         /* must be 0                                   */
 } corr_config;
 
 /* Bytes of device workspace a plan needs for `cfg`.  Host only. */
@@ -115,13 +136,17 @@ corr_status corr_create(const corr_config *cfg, void *d_workspace, size_t ws_byt
 corr_status corr_destroy(corr_plan *plan);
 
 /* F-stage (Sec. 4, steps 1 and 2; the unpack transpose is fused into it).
- * d_volt: device int8 real voltages, [n_blocks*fft_size][n_inputs], time-major
- * with the input index fastest (the aggregated order of Sec. 3).  Each block
- * of fft_size samples of each input is transformed by a real DFT (forward
- * sign, unnormalised, no window); channels k = 0..fft_size/2-1 are kept (DC
- * kept, Nyquist dropped), scaled by requant_scale, rounded half to even,
- * clipped to +-max_abs and appended as one CI8 time sample per block to the
- * ring [n_channels][n_inputs][.] in the workspace.
+ * d_volt: device samples in cfg.volt_format, [n_blocks*fft_size][n_inputs],
+ * time-major with the input index fastest (the aggregated order of Sec. 3):
+ * int8 bytes (CORR_VOLT_R8), 16-bit words (CORR_VOLT_CW16) or bytes
+ * (CORR_VOLT_CB8).  Each block of fft_size samples of each input is
+ * transformed by a DFT (forward sign, unnormalised, no window).  Real input:
+ * channels k = 0..fft_size/2-1 are kept (DC kept, Nyquist dropped).  Complex
+ * input (Sec. 2: N_C samples give N_C channels): every k = 0..fft_size-1, in
+ * natural order (DC first, negative frequencies in the upper half).  The
+ * spectra are scaled by requant_scale, rounded half to even, clipped to
+ * +-max_abs and appended as one CI8 time sample per block to the ring
+ * [n_channels][n_inputs][.] in the workspace.
  * first_seq: sequence number of the first block; it must equal the number
  * that follows the previous call's last block (any value on the first call
  * or after corr_seq_reset), else CORR_E_SEQ and nothing is done.
@@ -129,8 +154,26 @@ corr_status corr_destroy(corr_plan *plan);
  * first).  d_spectra_dbg: optional device float32 [n_channels][n_inputs]
  * [n_blocks][2] that receives the spectra before requantisation (NULL in
  * production; parity tests use it).  Asynchronous. */
-corr_status corr_channelise(corr_plan *plan, const int8_t *d_volt, int64_t n_blocks,
+corr_status corr_channelise(corr_plan *plan, const void *d_volt, int64_t n_blocks,
                             uint64_t first_seq, float *d_spectra_dbg);
+
+/* Aggregation of capture streams (Sec. 3).  d_records: device uint16
+ * [n_streams][n_records][1 + words_per_record]: in every stream, each record
+ * is one marker/counter word followed by one sample word per receiver input.
+ * The marker words are dropped and the streams interleaved so that the
+ * n_streams*words_per_record samples of one time instant are adjacent:
+ * d_out[r][s*words_per_record + w] = record r of stream s, word 1 + w
+ * (device uint16 [n_records][n_streams*words_per_record], caller-owned; the
+ * corr_channelise input for CORR_VOLT_CW16).  The marker is read as a 16-bit
+ * record counter: d_bad_records (optional device uint32, may be NULL) is
+ * incremented once per record whose counter is not (first_counter + r) mod
+ * 2^16 in at least one stream; the data are copied regardless.  No plan
+ * needed; asynchronous on hip_stream (NULL = default stream).
+ * CORR_E_INVAL for n_streams or words_per_record < 1, n_records < 0, or a
+ * NULL buffer with n_records > 0. */
+corr_status corr_aggregate_w16(const uint16_t *d_records, int32_t n_streams, int32_t words_per_record,
+                               int64_t n_records, uint32_t first_counter, uint16_t *d_out,
+                               uint32_t *d_bad_records, void *hip_stream);
 
 /* Accept any first_seq on the next corr_channelise call. */
 corr_status corr_seq_reset(corr_plan *plan);

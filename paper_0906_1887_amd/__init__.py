@@ -10,7 +10,7 @@ from __future__ import annotations
 from . import _lib
 from ._lib import (CORR_CF32, CORR_CI8, CORR_DUMP_FOLD, CORR_DUMP_INTEG, CORR_DUMP_LONGRUN,
                    CORR_DUMP_NO_RESET, CORR_X_F8, CORR_X_F16, CORR_X_FP32, CORR_X_I8, CorrError,
-                   corr_channelise, corr_config, corr_correlate, corr_create, corr_destroy, corr_dump,
+                   corr_aggregate_w16, corr_channelise, corr_config, corr_correlate, corr_create, corr_destroy, corr_dump,
                    corr_dump_bytes, corr_job_desc, corr_ring_read, corr_sched_create, corr_sched_destroy,
                    corr_sched_now, corr_sched_poll, corr_sched_stats, corr_sched_submit, corr_seq_reset,
                    corr_stage_read, corr_status_str, corr_workspace_bytes)
@@ -20,16 +20,18 @@ __all__ = [
     "corr_channelise", "corr_seq_reset", "corr_correlate", "corr_dump", "corr_ring_read", "corr_stage_read",
     "corr_dump_bytes", "corr_job_desc", "corr_sched_now", "corr_sched_create", "corr_sched_submit",
     "corr_sched_poll", "corr_sched_stats", "corr_sched_destroy", "Scheduler",
-    "corr_status_str", "ENGINES", "SAMPLE_TYPES",
+    "corr_status_str", "ENGINES", "SAMPLE_TYPES", "VOLT_FORMATS", "corr_aggregate_w16", "aggregate_w16",
 ]
 
 ENGINES = {"fp32": CORR_X_FP32, "i8": CORR_X_I8, "f16": CORR_X_F16, "f8": CORR_X_F8}
 SAMPLE_TYPES = {"cf32": CORR_CF32, "ci8": CORR_CI8}
+# F-stage input formats: real int8; complex 5+5-bit in 16-bit words; complex 4+4-bit bytes
+VOLT_FORMATS = {"r8": 0, "cw16": 1, "cb8": 2}
 
 
 def make_config(n_inputs: int, n_channels: int, engine: str = "i8", sample_type: str = "ci8",
                 fft_size: int = 0, max_abs: int = 7, requant_scale: float = 0.0,
-                ring_samples: int = 0, fp64_longrun: bool = False) -> corr_config:
+                ring_samples: int = 0, fp64_longrun: bool = False, volt_format: str = "r8") -> corr_config:
     c = corr_config()
     c.n_inputs = n_inputs
     c.n_channels = n_channels
@@ -40,7 +42,28 @@ def make_config(n_inputs: int, n_channels: int, engine: str = "i8", sample_type:
     c.requant_scale = requant_scale
     c.fp64_longrun = int(bool(fp64_longrun))
     c.ring_samples = ring_samples
+    c.volt_format = VOLT_FORMATS[volt_format]
     return c
+
+
+def aggregate_w16(records, first_counter: int = 0, out=None, bad=None):
+    """Drop the marker words of capture-stream records and interleave the
+    streams (the aggregation of Sec. 3), on the records' device and current
+    stream.  records: uint16/int16 device tensor [n_streams][n_records][1 + w].
+    Returns (out [n_records][n_streams * w] of the same dtype, bad: uint32 device
+    tensor [1] counting records whose marker/counter word is not first_counter + r
+    mod 2^16 in some stream; accumulates into a given ``bad``)."""
+    import torch
+
+    assert records.dim() == 3 and records.is_contiguous() and records.element_size() == 2
+    ns, nr, wp1 = records.shape
+    if out is None:
+        out = torch.empty((nr, ns * (wp1 - 1)), dtype=records.dtype, device=records.device)
+    if bad is None:
+        bad = torch.zeros(1, dtype=torch.uint32, device=records.device)
+    stream = torch.cuda.current_stream(records.device).cuda_stream
+    corr_aggregate_w16(records.data_ptr(), ns, wp1 - 1, nr, first_counter, out.data_ptr(), bad.data_ptr(), stream)
+    return out, bad
 
 
 class Correlator:
@@ -53,7 +76,7 @@ class Correlator:
 
     def __init__(self, n_inputs: int, n_channels: int, engine: str = "i8", sample_type: str = "ci8",
                  fft_size: int = 0, max_abs: int = 7, requant_scale: float = 0.0, ring_samples: int = 0,
-                 fp64_longrun: bool = False, device: str = "cuda:0"):
+                 fp64_longrun: bool = False, device: str = "cuda:0", volt_format: str = "r8"):
         import torch
 
         self._torch = torch
@@ -62,7 +85,8 @@ class Correlator:
         self.n_channels = n_channels
         self.engine = engine
         self.cfg = make_config(n_inputs, n_channels, engine, sample_type, fft_size, max_abs,
-                               requant_scale, ring_samples, fp64_longrun)
+                               requant_scale, ring_samples, fp64_longrun, volt_format)
+        self.volt_format = volt_format
         self.ws_bytes = corr_workspace_bytes(self.cfg)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
@@ -72,7 +96,8 @@ class Correlator:
     # -- plan calls ---------------------------------------------------------
     def channelise(self, volt, first_seq: int, spectra_dbg=None) -> None:
         t = self._torch
-        assert volt.dtype == t.int8 and volt.is_contiguous() and volt.device == self.device
+        want = {"r8": (t.int8,), "cw16": (t.int16, t.uint16), "cb8": (t.uint8, t.int8)}[self.volt_format]
+        assert volt.dtype in want and volt.is_contiguous() and volt.device == self.device
         n_blocks = volt.shape[0] // self.cfg.fft_size
         dbg = 0
         if spectra_dbg is not None:

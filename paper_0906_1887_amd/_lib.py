@@ -36,7 +36,7 @@ EXPORTED = [
     "corr_workspace_bytes", "corr_create", "corr_destroy", "corr_channelise", "corr_seq_reset",
     "corr_correlate", "corr_dump", "corr_ring_read", "corr_stage_read", "corr_dump_bytes", "corr_status_str",
     "corr_sched_now", "corr_sched_create", "corr_sched_submit", "corr_sched_poll", "corr_sched_stats",
-    "corr_sched_destroy",
+    "corr_sched_destroy", "corr_aggregate_w16",
 ]
 
 
@@ -51,6 +51,8 @@ class corr_config(ctypes.Structure):
         ("requant_scale", ctypes.c_float),
         ("fp64_longrun", ctypes.c_int32),
         ("ring_samples", ctypes.c_int64),
+        ("volt_format", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -95,6 +97,7 @@ def lib():
         L.corr_destroy.argtypes = [P]
         L.corr_channelise.argtypes = [P, P, I64, ctypes.c_uint64, P]
         L.corr_seq_reset.argtypes = [P]
+        L.corr_aggregate_w16.argtypes = [P, I32, I32, I64, ctypes.c_uint32, P, P, P]
         L.corr_correlate.argtypes = [P, P, I64, I64]
         L.corr_dump.argtypes = [P, I32, P, I32, ctypes.POINTER(I64), ctypes.POINTER(I32)]
         L.corr_ring_read.argtypes = [P, P, I32, ctypes.POINTER(I64)]
@@ -141,6 +144,14 @@ def corr_create(cfg: corr_config, d_workspace: int, ws_bytes: int, hip_stream: i
 
 def corr_destroy(plan: int) -> None:
     _check(lib().corr_destroy(ctypes.c_void_p(plan)), "corr_destroy")
+
+
+def corr_aggregate_w16(d_records: int, n_streams: int, words_per_record: int, n_records: int,
+                       first_counter: int, d_out: int, d_bad_records: int = 0, stream: int = 0) -> None:
+    _check(lib().corr_aggregate_w16(ctypes.c_void_p(d_records), n_streams, words_per_record, n_records,
+                                    first_counter & 0xFFFFFFFF, ctypes.c_void_p(d_out),
+                                    ctypes.c_void_p(d_bad_records or None), ctypes.c_void_p(stream or None)),
+           "corr_aggregate_w16")
 
 
 def corr_channelise(plan: int, d_volt: int, n_blocks: int, first_seq: int, d_spectra_dbg: int = 0) -> None:

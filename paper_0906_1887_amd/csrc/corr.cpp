@@ -68,9 +68,18 @@ corr_status validate(const corr_config* c) {
     if (c->sample_type != CORR_CI8 && c->fft_size == 0) return CORR_E_INVAL;
     if (c->max_abs < 1) return CORR_E_INVAL;  // int32 bound needs a declared range
   }
+  if (c->reserved != 0) return CORR_E_INVAL;
+  if (c->fft_size == 0 && c->volt_format != CORR_VOLT_R8) return CORR_E_INVAL;
   if (c->fft_size != 0) {
-    if (c->fft_size != 2 * c->n_channels) return CORR_E_INVAL;
-    if (c->fft_size != 256) return CORR_E_UNSUPPORTED;
+    if (c->volt_format == CORR_VOLT_R8) {
+      if (c->fft_size != 2 * c->n_channels) return CORR_E_INVAL;
+      if (c->fft_size != 256) return CORR_E_UNSUPPORTED;
+    } else if (c->volt_format == CORR_VOLT_CW16 || c->volt_format == CORR_VOLT_CB8) {
+      if (c->fft_size != c->n_channels) return CORR_E_INVAL;
+      if (c->fft_size != 128) return CORR_E_UNSUPPORTED;
+    } else {
+      return CORR_E_INVAL;
+    }
     if (c->max_abs < 1) return CORR_E_INVAL;
     if (!(c->requant_scale > 0.0f) || !std::isfinite(c->requant_scale)) return CORR_E_INVAL;
     if (c->ring_samples < 1) return CORR_E_INVAL;
@@ -287,6 +296,16 @@ corr_status corr_destroy(corr_plan* plan) {
   return CORR_OK;
 }
 
+corr_status corr_aggregate_w16(const uint16_t* d_records, int32_t n_streams, int32_t words_per_record,
+                               int64_t n_records, uint32_t first_counter, uint16_t* d_out, uint32_t* d_bad_records,
+                               void* hip_stream) {
+  if (n_streams < 1 || words_per_record < 1 || n_records < 0) return CORR_E_INVAL;
+  if (n_records > 0 && (!d_records || !d_out)) return CORR_E_INVAL;
+  const hipError_t e = corr::launch_aggregate_w16(d_records, n_streams, words_per_record, n_records, first_counter,
+                                                  d_out, d_bad_records, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? CORR_OK : (e == hipErrorInvalidValue ? CORR_E_INVAL : CORR_E_HIP);
+}
+
 corr_status corr_seq_reset(corr_plan* p) {
   if (!p) return CORR_E_INVAL;
   if (p->error) return CORR_E_STATE;
@@ -294,7 +313,7 @@ corr_status corr_seq_reset(corr_plan* p) {
   return CORR_OK;
 }
 
-corr_status corr_channelise(corr_plan* p, const int8_t* d_volt, int64_t n_blocks, uint64_t first_seq,
+corr_status corr_channelise(corr_plan* p, const void* d_volt, int64_t n_blocks, uint64_t first_seq,
                             float* d_spectra_dbg) {
   try {
     if (!p) return CORR_E_INVAL;
@@ -316,7 +335,9 @@ corr_status corr_channelise(corr_plan* p, const int8_t* d_volt, int64_t n_blocks
       fc.n_in = c.n_inputs;
       fc.scale = c.requant_scale;
       fc.max_abs = (float)c.max_abs;
-      const hipError_t e = corr::launch_fstage_call(fc, p->stream);
+      fc.format = c.volt_format;
+      const hipError_t e = (c.volt_format == CORR_VOLT_R8) ? corr::launch_fstage_call(fc, p->stream)
+                                                          : corr::launch_fstage_complex(fc, p->stream);
       if (e != hipSuccess) return hip_fail(p, e);
     }
     p->ring_fill += n_blocks;

@@ -21,7 +21,7 @@ hipError_t launch_fold_f64(double* L, const void* V, int64_t n_scalars, bool is_
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
 
 struct FStageCall {
-  const int8_t* volt;
+  const void* volt;        // real int8 (format 0), 16-bit 5+5 words (1) or 4+4 bytes (2)
   const float2* twiddle;
   int8_t* ring;
   float* dbg;
@@ -31,8 +31,12 @@ struct FStageCall {
   int32_t n_in;
   float scale;
   float max_abs;
+  int32_t format;          // 0: real 256-point F-stage; 1, 2: complex 128-point F-stage
 };
 hipError_t launch_fstage_call(const FStageCall& c, hipStream_t s);
+hipError_t launch_fstage_complex(const FStageCall& c, hipStream_t s);
+hipError_t launch_aggregate_w16(const uint16_t* rec, int32_t n_streams, int32_t w_per, int64_t n_rec,
+                                uint32_t first_counter, uint16_t* out, uint32_t* bad, hipStream_t s);
 
 struct LowpCall {
   const float* x;          // complex float32 [n_ch][n_in][row_stride]

@@ -20,6 +20,11 @@ Signals (all seeded, all reproducible):
   reads the uploaded array).
 * ``complex_float`` -- complex Gaussian float inputs with per-input gains
   and coherent pairs (numpy PCG64, host only, uploaded).
+* ``capture_records`` / ``complex_bytes`` -- the prototype's recorded
+  complex samples: Gaussian noise with a correlated component on a subset of
+  inputs and a complex tone, rounded and clipped to 5-bit (or 4-bit) two's
+  complement and packed as 16-bit words in marker-led records (or bytes)
+  (numpy PCG64, host only, uploaded).
 """
 from __future__ import annotations
 
@@ -333,3 +338,55 @@ class DeviceGen:
                                      seed & 0xFFFFFFFFFFFFFFFF, ctypes.byref(s), ctypes.c_void_p(stream))
         if rc != 0:
             raise RuntimeError(f"synth_fill_ci8 failed ({rc})")
+
+
+# ---------------------------------------------------------------------------
+# The prototype's recorded complex samples (5+5-bit words in records; 4+4-bit
+# bytes).  Field layout: re in the upper field, im in the lower field, two's
+# complement; words carry arbitrary bits above bit 9.
+# ---------------------------------------------------------------------------
+def complex_levels(seed: int, index: int, n_samples: int, n_inputs: int, bits: int = 5,
+                   sigma: float = 4.0, rho: float = 0.1, n_corr: int = 8, tone_bin: int = 19,
+                   tone_amp: float = 1.5, fft_size: int = 128) -> np.ndarray:
+    """int8 [n_samples][n_inputs][2] (re, im) levels in [-2^(bits-1), 2^(bits-1)-1]:
+    rint(sigma*(a n + b c) + tone), n, c ~ CN(0, 1) per part, c common to inputs
+    0..n_corr-1 (a = sqrt(1-rho), b = sqrt(rho) there), the tone
+    tone_amp*exp(2 pi i tone_bin t / fft_size) on every input."""
+    rng = np.random.default_rng([seed, index, bits])
+    lo, hi = -(1 << (bits - 1)), (1 << (bits - 1)) - 1
+    a = np.ones(n_inputs)
+    b = np.zeros(n_inputs)
+    a[:n_corr] = math.sqrt(1.0 - rho)
+    b[:n_corr] = math.sqrt(rho)
+    n = rng.standard_normal((n_samples, n_inputs, 2)) * math.sqrt(0.5)
+    c = rng.standard_normal((n_samples, 1, 2)) * math.sqrt(0.5)
+    v = sigma * (a[None, :, None] * n + b[None, :, None] * c)
+    ph = 2.0 * np.pi * ((tone_bin * np.arange(n_samples)) % fft_size) / fft_size
+    v[..., 0] += tone_amp * np.cos(ph)[:, None]
+    v[..., 1] += tone_amp * np.sin(ph)[:, None]
+    return np.clip(np.rint(v), lo, hi).astype(np.int8)
+
+
+def capture_records(seed: int, index: int, n_records: int, n_streams: int = 4, w_per: int = 16,
+                    first_counter: int = 0, **kw):
+    """(records uint16 [n_streams][n_records][1 + w_per], levels int8 [n_records][n_streams*w_per][2]).
+    Word 0 of record r is (first_counter + r) mod 2^16; data words pack the 5-bit
+    levels as (re & 31) << 5 | (im & 31) with random bits 15..10."""
+    lv = complex_levels(seed, index, n_records, n_streams * w_per, bits=5, **kw)
+    rng = np.random.default_rng([seed, index, 0xC0FFEE])
+    junk = rng.integers(0, 64, size=(n_records, n_streams * w_per)).astype(np.uint16) << 10
+    words = (((lv[..., 0].astype(np.int64) & 31) << 5) | (lv[..., 1].astype(np.int64) & 31)).astype(np.uint16)
+    words |= junk
+    rec = np.empty((n_streams, n_records, 1 + w_per), dtype=np.uint16)
+    rec[:, :, 0] = ((first_counter + np.arange(n_records)) & 0xFFFF).astype(np.uint16)[None, :]
+    rec[:, :, 1:] = words.reshape(n_records, n_streams, w_per).transpose(1, 0, 2)
+    return rec, lv
+
+
+def complex_bytes(seed: int, index: int, n_samples: int, n_inputs: int, **kw):
+    """(bytes uint8 [n_samples][n_inputs], levels int8 [n_samples][n_inputs][2]): 4-bit
+    levels packed as (re & 15) << 4 | (im & 15)."""
+    kw.setdefault("sigma", 2.0)
+    lv = complex_levels(seed, index, n_samples, n_inputs, bits=4, **kw)
+    b = (((lv[..., 0].astype(np.int64) & 15) << 4) | (lv[..., 1].astype(np.int64) & 15)).astype(np.uint8)
+    return b, lv
