@@ -191,7 +191,102 @@ def other_configs(dev, stream):
     out.update(c1_config(dev, stream))
     out.update(c2_config(dev, stream))
     out.update(c4_config(dev, stream))
+    out.update(prototype_config(dev, stream))
     return out
+
+
+def prototype_config(dev, stream, reps=10):
+    """One second of the paper's prototype (Table 3's workload): 4 capture
+    streams of 1.28 M records (marker + 16 words of 5+5-bit complex samples),
+    64 inputs, 128 channels.  Times each step on the device: aggregation,
+    complex F-stage (16-bit words; and the 1-byte mode), and the int8 and
+    plain FP32 X-engines on the F-stage's ring."""
+    import torch
+    from paper_0906_1887_amd import Correlator, aggregate_w16, perfmodel
+    hbm = perfmodel.MI355X["hbm_Bps"]
+    ns, wp, nr = 4, 16, 1_280_000
+    n_in, nb = ns * wp, nr // 128
+    g = torch.Generator(device=dev).manual_seed(11)
+    # any 16-bit word is a valid sample (bits above 9 are ignored); counters in word 0
+    rec = torch.randint(-32768, 32768, (ns, nr, 1 + wp), dtype=torch.int32, device=dev, generator=g).to(torch.int16)
+    rec[:, :, 0] = (torch.arange(nr, device=dev, dtype=torch.int32) & 0xFFFF).to(torch.int16)[None, :]
+    rec = rec.contiguous()
+    agg, bad = aggregate_w16(rec)
+    b8 = torch.randint(0, 256, (nr, n_in), dtype=torch.int32, device=dev, generator=g).to(torch.uint8)
+    s_req = float(torch.tensor(1.0 / 16.0, dtype=torch.float32))
+    plans = {
+        "i8": Correlator(n_in, 128, engine="i8", fft_size=128, max_abs=7, requant_scale=s_req, ring_samples=nb,
+                         device=str(dev), volt_format="cw16"),
+        "fp32": Correlator(n_in, 128, engine="fp32", fft_size=128, max_abs=7, requant_scale=s_req,
+                           ring_samples=nb, device=str(dev), volt_format="cw16"),
+        "b8": Correlator(n_in, 128, engine="i8", fft_size=128, max_abs=7, requant_scale=s_req, ring_samples=nb,
+                         device=str(dev), volt_format="cb8"),
+    }
+    seq = {k: 0 for k in plans}
+
+    def fx(key, volt):
+        c = plans[key]
+        c.channelise(volt, first_seq=seq[key])
+        seq[key] += nb
+        c.correlate(None)
+        c.dump(0)
+
+    for k, v in (("i8", agg), ("fp32", agg), ("b8", b8)):
+        fx(k, v)
+    torch.cuda.synchronize()
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    t = {"aggregate": 0.0, "fstage_w16": 0.0, "x_i8": 0.0, "x_fp32": 0.0, "fstage_b8": 0.0}
+    for _ in range(reps):
+        e = [ev() for _ in range(9)]
+        e[0].record(stream)
+        aggregate_w16(rec, out=agg, bad=bad)
+        e[1].record(stream)
+        c = plans["i8"]
+        c.channelise(agg, first_seq=seq["i8"])
+        e[2].record(stream)
+        c.correlate(None)
+        e[3].record(stream)
+        c.dump(0)
+        c = plans["fp32"]
+        c.channelise(agg, first_seq=seq["fp32"])
+        e[4].record(stream)
+        c.correlate(None)
+        e[5].record(stream)
+        c.dump(0)
+        c = plans["b8"]
+        e[6].record(stream)
+        c.channelise(b8, first_seq=seq["b8"])
+        e[7].record(stream)
+        c.correlate(None)
+        c.dump(0)
+        for k in seq:
+            seq[k] += nb
+        torch.cuda.synchronize()
+        t["aggregate"] += e[0].elapsed_time(e[1])
+        t["fstage_w16"] += e[1].elapsed_time(e[2])
+        t["x_i8"] += e[2].elapsed_time(e[3])
+        t["x_fp32"] += e[4].elapsed_time(e[5])
+        t["fstage_b8"] += e[6].elapsed_time(e[7])
+    t = {k: v / reps for k, v in t.items()}
+    for c in plans.values():
+        c.close()
+    cm = perfmodel.xengine_cmac(128, n_in, nb)
+    agg_bytes = ns * nr * (1 + wp) * 2 + nr * n_in * 2
+    f16_bytes = nr * n_in * 2 + 128 * n_in * nb * 2
+    f8_bytes = nr * n_in + 128 * n_in * nb * 2
+    paper = {"unpack": 53.0, "fft": 53.0, "cmac_gp4": 185.0, "cmac_pp": 494.0}
+    return {"prototype_1s": {
+        "ms": t,
+        "total_ms_w16_i8": t["aggregate"] + t["fstage_w16"] + t["x_i8"],
+        "aggregate_frac_of_hbm": agg_bytes / (t["aggregate"] / 1e3) / hbm,
+        "fstage_w16_frac_of_hbm": f16_bytes / (t["fstage_w16"] / 1e3) / hbm,
+        "fstage_b8_frac_of_hbm": f8_bytes / (t["fstage_b8"] / 1e3) / hbm,
+        "x_i8_tcmac_s": cm / (t["x_i8"] / 1e3) / 1e12,
+        "x_fp32_tcmac_s": cm / (t["x_fp32"] / 1e3) / 1e12,
+        "paper_c1060_ms": paper,
+        "note": "1 s of 64 inputs x 1.28 MHz complex samples, 128 channels (10000 spectra per input); "
+                "the paper's Table 3 (Tesla C1060, FP32 CMAC) is context: its CMAC is on FP32 spectra, "
+                "ours on the F-stage's 4-bit requantised ring"}}
 
 
 def c1_config(dev, stream):
@@ -313,10 +408,11 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-other-configs", action="store_true")
-    ap.add_argument("--mode", choices=["bench", "copy", "c2"], default="bench",
+    ap.add_argument("--mode", choices=["bench", "copy", "c2", "proto"], default="bench",
                     help="copy: only a 1 GiB device-to-device copy, the known-size reference for "
                          "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE counters; c2: only the C2 "
-                         "F-stage + X-engine timing (for profiling the F-stage)")
+                         "F-stage + X-engine timing (for profiling the F-stage); proto: only one second of "
+                         "the prototype's complex front end")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -342,6 +438,9 @@ def main() -> int:
     stream = torch.cuda.current_stream(dev)
     if args.mode == "c2":
         print(json.dumps({"mode": "c2", **c2_config(dev, stream, reps=args.steps)}))
+        return 0
+    if args.mode == "proto":
+        print(json.dumps({"mode": "proto", **prototype_config(dev, stream, reps=args.steps)}))
         return 0
     log("generating input on device")
     x = torch.empty((N_CH, N_IN, N_T, 2), dtype=torch.int8, device=dev)

@@ -45,10 +45,55 @@ __global__ __launch_bounds__(256) void aggregate_w16_kernel(const uint16_t* __re
   }
 }
 
+// The prototype's layout (16 words per record, up to 4 streams): a workgroup
+// copies 256 records of every stream into LDS with contiguous dword loads
+// (256 records x 34 bytes is a whole number of dwords), then thread r packs
+// record r of every stream into its output row (whole 16-byte stores) and
+// checks the counters.
+constexpr int kAggRec = 256;
+constexpr int kAggWords = 17;  // marker + 16 samples
+__global__ __launch_bounds__(256) void aggregate_w16_rows_kernel(const uint16_t* __restrict__ rec, int32_t n_streams,
+                                                                 int64_t n_rec, uint32_t first_counter,
+                                                                 uint16_t* __restrict__ out,
+                                                                 uint32_t* __restrict__ bad) {
+  __shared__ uint32_t buf[4][kAggRec * kAggWords / 2];  // 34 KB
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * kAggRec;
+  const int nr = (int)min((int64_t)kAggRec, n_rec - r0);  // even: n_rec and r0 are
+  const int nd = nr * kAggWords / 2;
+  for (int s = 0; s < n_streams; ++s) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(rec + ((int64_t)s * n_rec + r0) * kAggWords);
+    for (int d = tid; d < nd; d += 256) buf[s][d] = src[d];
+  }
+  __syncthreads();
+  if (tid >= nr) return;
+  const uint16_t want = (uint16_t)((first_counter + (uint64_t)(r0 + tid)) & 0xFFFFu);
+  bool mismatch = false;
+  uint4* dst = reinterpret_cast<uint4*>(out + (r0 + tid) * (int64_t)n_streams * 16);
+  for (int s = 0; s < n_streams; ++s) {
+    const uint16_t* b = reinterpret_cast<const uint16_t*>(buf[s]) + tid * kAggWords;
+    mismatch |= (b[0] != want);
+    uint32_t wd[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) wd[q] = (uint32_t)b[1 + 2 * q] | ((uint32_t)b[2 + 2 * q] << 16);
+    dst[2 * s] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+    dst[2 * s + 1] = make_uint4(wd[4], wd[5], wd[6], wd[7]);
+  }
+  if (mismatch && bad != nullptr) atomicAdd(bad, 1u);
+}
+
 hipError_t launch_aggregate_w16(const uint16_t* rec, int32_t n_streams, int32_t w_per, int64_t n_rec,
                                 uint32_t first_counter, uint16_t* out, uint32_t* bad, hipStream_t s) {
   const int64_t total = n_rec * n_streams * (int64_t)w_per;
   if (total <= 0) return hipSuccess;
+  if (w_per == 16 && n_streams <= 4 && n_rec % 2 == 0 && (reinterpret_cast<uintptr_t>(rec) & 3) == 0 &&
+      (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+    const int64_t grid = (n_rec + kAggRec - 1) / kAggRec;
+    if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(aggregate_w16_rows_kernel, dim3((unsigned)grid), dim3(256), 0, s, rec, n_streams, n_rec,
+                       first_counter, out, bad);
+    return hipGetLastError();
+  }
   const int64_t grid = (total + 255) / 256;
   if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
   hipLaunchKernelGGL(aggregate_w16_kernel, dim3((unsigned)grid), dim3(256), 0, s, rec, n_streams, w_per, n_rec,
