@@ -192,7 +192,50 @@ def other_configs(dev, stream):
     out.update(c2_config(dev, stream))
     out.update(c4_config(dev, stream))
     out.update(prototype_config(dev, stream))
+    out.update(designs_config(dev, stream))
     return out
+
+
+def designs_config(dev, stream, reps=3):
+    """The paper's CMAC design comparison (Tables 2-4) on this GPU: one
+    second of the prototype's spectra (64 inputs, 128 channels, 10000 spectra,
+    complex float32 laid out [t][input][channel]) through pair parallel, hybrid
+    group and group parallel, against the memory-bound model, beside this
+    library's tiled plain-FP32 engine on the same spectra ([channel][input][t])."""
+    import torch
+    from paper_0906_1887_amd import Correlator, cmac_design, perfmodel
+    n_in, n_ch, T, B = 64, 128, 10000, 1.28e6
+    g = torch.Generator(device=dev).manual_seed(12)
+    xs = torch.randn((T, n_in, n_ch, 2), device=dev, generator=g)
+    out = torch.zeros((n_ch, n_in * (n_in + 1) // 2, 2), dtype=torch.float32, device=dev)
+    hbm = perfmodel.MI355X["hbm_Bps"]
+    paper_c1060 = {"PP": (2.6, 3.1), "HG2": (3.3, 4.1), "HG4": (3.8, 4.9), "GP2": (4.8, 6.1), "GP4": (6.9, 12.0)}
+    res = {}
+    for name, key in (("pp", "PP"), ("hg2", "HG2"), ("hg4", "HG4"), ("gp2", "GP2"), ("gp4", "GP4")):
+        cmac_design(name, xs, out=out)
+        ms = time_events(lambda: cmac_design(name, xs, out=out), reps, stream)
+        eps = perfmodel.PAPER_EPS[key]
+        b_act = B / (ms / 1e3)
+        b_th = perfmodel.max_signal_bandwidth(hbm, eps, n_in)
+        res[key] = {"ms": ms, "eps": eps, "actual_MHz": b_act / 1e6, "theoretical_MHz": b_th / 1e6,
+                    "frac": b_act / b_th, "tcmac_s": perfmodel.xengine_cmac(n_ch, n_in, T) / (ms / 1e3) / 1e12,
+                    "paper_c1060_MHz": {"actual": paper_c1060[key][0], "theoretical": paper_c1060[key][1]}}
+    xc = xs.permute(2, 1, 0, 3).contiguous()              # [ch][input][t][2]
+    del xs
+    c = Correlator(n_in, n_ch, engine="fp32", sample_type="cf32", max_abs=0, device=str(dev))
+
+    def tiled():
+        c.correlate(xc)
+        c.dump(0)
+    tiled()
+    ms = time_events(tiled, reps, stream)
+    c.close()
+    res["tiled_fp32"] = {"ms": ms, "actual_MHz": B / (ms / 1e3) / 1e6,
+                         "tcmac_s": perfmodel.xengine_cmac(n_ch, n_in, T) / (ms / 1e3) / 1e12,
+                         "note": "this library's FP32 engine (LDS-tiled 64x64, split K) on [channel][input][t]"}
+    return {"designs_1s": {**res, "note": "1 s of 64 inputs x 1.28 MHz, 128 channels; theoretical = 8 TB/s / "
+                                          "(4 eps N_I (N_I+1)) (the paper's memory-bound model); actual = "
+                                          "1.28 MHz x (1 s / time); the paper's C1060 row for context"}}
 
 
 def prototype_config(dev, stream, reps=10):
@@ -408,11 +451,11 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-other-configs", action="store_true")
-    ap.add_argument("--mode", choices=["bench", "copy", "c2", "proto"], default="bench",
+    ap.add_argument("--mode", choices=["bench", "copy", "c2", "proto", "designs"], default="bench",
                     help="copy: only a 1 GiB device-to-device copy, the known-size reference for "
                          "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE counters; c2: only the C2 "
                          "F-stage + X-engine timing (for profiling the F-stage); proto: only one second of "
-                         "the prototype's complex front end")
+                         "the prototype's complex front end; designs: only the paper's CMAC designs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -441,6 +484,9 @@ def main() -> int:
         return 0
     if args.mode == "proto":
         print(json.dumps({"mode": "proto", **prototype_config(dev, stream, reps=args.steps)}))
+        return 0
+    if args.mode == "designs":
+        print(json.dumps({"mode": "designs", **designs_config(dev, stream, reps=args.steps)}))
         return 0
     log("generating input on device")
     x = torch.empty((N_CH, N_IN, N_T, 2), dtype=torch.int8, device=dev)

@@ -175,6 +175,33 @@ corr_status corr_aggregate_w16(const uint16_t *d_records, int32_t n_streams, int
                                int64_t n_records, uint32_t first_counter, uint16_t *d_out,
                                uint32_t *d_bad_records, void *hip_stream);
 
+/* The paper's three CMAC designs (Sec. 4, Tables 2-4), kept as described so
+ * that their comparison can be repeated on this hardware beside the tiled
+ * engines of corr_correlate.  d_spectra: device complex float32
+ * [n_samples][n_inputs][n_channels][2] (channel fastest: the FFT output order
+ * of Fig. 1, one thread per channel).  Adds (accumulate != 0) or writes, for
+ * every channel c and pair j <= i, sum over the n_samples of x_i conj(x_j)
+ * (FP32 FMA, sequential in time) into d_out [n_channels][P][2] float32 (P =
+ * n_inputs(n_inputs+1)/2, b(i,j) = i(i+1)/2 + j; autos get im = 0).
+ *   design CORR_DESIGN_PP (group 1): pair parallel, 2 global reads per
+ *     product, pair decoded from a constant-memory table;
+ *   CORR_DESIGN_GP (group 2 or 4): group parallel, 2G reads per G^2
+ *     products, i-axis values shared through LDS with a barrier per sample;
+ *   CORR_DESIGN_HG (group 2 or 4): hybrid group, G+1 reads per G products,
+ *     LDS used as register space (no barrier), redundant half exits.
+ * CORR_E_INVAL for an unknown design, a group not allowed for it, n_inputs not
+ * a multiple of the group, n_inputs or n_channels < 1, n_samples < 0 or a
+ * NULL buffer; CORR_E_UNSUPPORTED for n_inputs > 128.  No plan needed;
+ * asynchronous on hip_stream (NULL = default stream). */
+typedef enum {
+    CORR_DESIGN_PP = 0,
+    CORR_DESIGN_GP = 1,
+    CORR_DESIGN_HG = 2
+} corr_design_t;
+corr_status corr_cmac_design(int32_t design, int32_t group, const float *d_spectra, int64_t n_samples,
+                             int32_t n_inputs, int32_t n_channels, float *d_out, int32_t accumulate,
+                             void *hip_stream);
+
 /* Accept any first_seq on the next corr_channelise call. */
 corr_status corr_seq_reset(corr_plan *plan);
 

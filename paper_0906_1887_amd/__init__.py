@@ -10,7 +10,7 @@ from __future__ import annotations
 from . import _lib
 from ._lib import (CORR_CF32, CORR_CI8, CORR_DUMP_FOLD, CORR_DUMP_INTEG, CORR_DUMP_LONGRUN,
                    CORR_DUMP_NO_RESET, CORR_X_F8, CORR_X_F16, CORR_X_FP32, CORR_X_I8, CorrError,
-                   corr_aggregate_w16, corr_channelise, corr_config, corr_correlate, corr_create, corr_destroy, corr_dump,
+                   corr_aggregate_w16, corr_channelise, corr_cmac_design, corr_config, corr_correlate, corr_create, corr_destroy, corr_dump,
                    corr_dump_bytes, corr_job_desc, corr_ring_read, corr_sched_create, corr_sched_destroy,
                    corr_sched_now, corr_sched_poll, corr_sched_stats, corr_sched_submit, corr_seq_reset,
                    corr_stage_read, corr_status_str, corr_workspace_bytes)
@@ -21,6 +21,7 @@ __all__ = [
     "corr_dump_bytes", "corr_job_desc", "corr_sched_now", "corr_sched_create", "corr_sched_submit",
     "corr_sched_poll", "corr_sched_stats", "corr_sched_destroy", "Scheduler",
     "corr_status_str", "ENGINES", "SAMPLE_TYPES", "VOLT_FORMATS", "corr_aggregate_w16", "aggregate_w16",
+    "corr_cmac_design", "cmac_design", "DESIGNS",
 ]
 
 ENGINES = {"fp32": CORR_X_FP32, "i8": CORR_X_I8, "f16": CORR_X_F16, "f8": CORR_X_F8}
@@ -64,6 +65,27 @@ def aggregate_w16(records, first_counter: int = 0, out=None, bad=None):
     stream = torch.cuda.current_stream(records.device).cuda_stream
     corr_aggregate_w16(records.data_ptr(), ns, wp1 - 1, nr, first_counter, out.data_ptr(), bad.data_ptr(), stream)
     return out, bad
+
+
+# The paper's CMAC designs: name -> (corr_design_t, group G)
+DESIGNS = {"pp": (0, 1), "gp2": (1, 2), "gp4": (1, 4), "hg2": (2, 2), "hg4": (2, 4)}
+
+
+def cmac_design(name: str, spectra, out=None, accumulate: bool = False):
+    """Run one of the paper's CMAC designs on complex float32 spectra laid out
+    [n_samples][n_inputs][n_channels][2] (a float32 device tensor), on the
+    current stream.  Returns out [n_channels][P][2] float32."""
+    import torch
+
+    design, group = DESIGNS[name]
+    assert spectra.dtype == torch.float32 and spectra.is_contiguous() and spectra.shape[-1] == 2
+    T, n_in, n_ch, _ = spectra.shape
+    P = n_in * (n_in + 1) // 2
+    if out is None:
+        out = torch.zeros((n_ch, P, 2), dtype=torch.float32, device=spectra.device)
+    stream = torch.cuda.current_stream(spectra.device).cuda_stream
+    corr_cmac_design(design, group, spectra.data_ptr(), T, n_in, n_ch, out.data_ptr(), accumulate, stream)
+    return out
 
 
 class Correlator:

@@ -36,7 +36,7 @@ EXPORTED = [
     "corr_workspace_bytes", "corr_create", "corr_destroy", "corr_channelise", "corr_seq_reset",
     "corr_correlate", "corr_dump", "corr_ring_read", "corr_stage_read", "corr_dump_bytes", "corr_status_str",
     "corr_sched_now", "corr_sched_create", "corr_sched_submit", "corr_sched_poll", "corr_sched_stats",
-    "corr_sched_destroy", "corr_aggregate_w16",
+    "corr_sched_destroy", "corr_aggregate_w16", "corr_cmac_design",
 ]
 
 
@@ -98,6 +98,7 @@ def lib():
         L.corr_channelise.argtypes = [P, P, I64, ctypes.c_uint64, P]
         L.corr_seq_reset.argtypes = [P]
         L.corr_aggregate_w16.argtypes = [P, I32, I32, I64, ctypes.c_uint32, P, P, P]
+        L.corr_cmac_design.argtypes = [I32, I32, P, I64, I32, I32, P, I32, P]
         L.corr_correlate.argtypes = [P, P, I64, I64]
         L.corr_dump.argtypes = [P, I32, P, I32, ctypes.POINTER(I64), ctypes.POINTER(I32)]
         L.corr_ring_read.argtypes = [P, P, I32, ctypes.POINTER(I64)]
@@ -152,6 +153,13 @@ def corr_aggregate_w16(d_records: int, n_streams: int, words_per_record: int, n_
                                     first_counter & 0xFFFFFFFF, ctypes.c_void_p(d_out),
                                     ctypes.c_void_p(d_bad_records or None), ctypes.c_void_p(stream or None)),
            "corr_aggregate_w16")
+
+
+def corr_cmac_design(design: int, group: int, d_spectra: int, n_samples: int, n_inputs: int, n_channels: int,
+                     d_out: int, accumulate: bool = False, stream: int = 0) -> None:
+    _check(lib().corr_cmac_design(design, group, ctypes.c_void_p(d_spectra), n_samples, n_inputs, n_channels,
+                                  ctypes.c_void_p(d_out), int(bool(accumulate)), ctypes.c_void_p(stream or None)),
+           "corr_cmac_design")
 
 
 def corr_channelise(plan: int, d_volt: int, n_blocks: int, first_seq: int, d_spectra_dbg: int = 0) -> None:

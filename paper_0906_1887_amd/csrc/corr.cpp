@@ -306,6 +306,20 @@ corr_status corr_aggregate_w16(const uint16_t* d_records, int32_t n_streams, int
   return e == hipSuccess ? CORR_OK : (e == hipErrorInvalidValue ? CORR_E_INVAL : CORR_E_HIP);
 }
 
+corr_status corr_cmac_design(int32_t design, int32_t group, const float* d_spectra, int64_t n_samples,
+                             int32_t n_inputs, int32_t n_channels, float* d_out, int32_t accumulate,
+                             void* hip_stream) {
+  if (design != CORR_DESIGN_PP && design != CORR_DESIGN_GP && design != CORR_DESIGN_HG) return CORR_E_INVAL;
+  if (design == CORR_DESIGN_PP ? group != 1 : (group != 2 && group != 4)) return CORR_E_INVAL;
+  if (n_inputs < 1 || n_channels < 1 || n_samples < 0 || n_inputs % group != 0) return CORR_E_INVAL;
+  if (!d_spectra || !d_out) return CORR_E_INVAL;
+  if (n_inputs > 128) return CORR_E_UNSUPPORTED;
+  const hipError_t e = corr::launch_cmac_design(design, group, reinterpret_cast<const float2*>(d_spectra), n_samples,
+                                                n_inputs, n_channels, reinterpret_cast<float2*>(d_out), accumulate,
+                                                static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? CORR_OK : (e == hipErrorInvalidValue ? CORR_E_INVAL : CORR_E_HIP);
+}
+
 corr_status corr_seq_reset(corr_plan* p) {
   if (!p) return CORR_E_INVAL;
   if (p->error) return CORR_E_STATE;

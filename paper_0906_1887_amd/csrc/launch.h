@@ -35,6 +35,8 @@ struct FStageCall {
 };
 hipError_t launch_fstage_call(const FStageCall& c, hipStream_t s);
 hipError_t launch_fstage_complex(const FStageCall& c, hipStream_t s);
+hipError_t launch_cmac_design(int design, int group, const float2* x, int64_t T, int n_in, int n_ch, float2* out,
+                              int accumulate, hipStream_t s);
 hipError_t launch_aggregate_w16(const uint16_t* rec, int32_t n_streams, int32_t w_per, int64_t n_rec,
                                 uint32_t first_counter, uint16_t* out, uint32_t* bad, hipStream_t s);
 
