@@ -49,6 +49,8 @@ def _load():
         lib.oracle_dft_real.argtypes = [P, I64, I64, I64, I64, P]
         lib.oracle_requant.argtypes = [P, I64, ctypes.c_double, ctypes.c_int32, P]
         lib.oracle_dft_complex.argtypes = [P, I64, I64, I64, P]
+        lib.oracle_pfb_coeffs.argtypes = [I64, I64, P]
+        lib.oracle_pfb_real.argtypes = [P, P, I64, I64, I64, I64, I64, P]
         lib.oracle_unpack_w16.argtypes = [P, I64, P]
         lib.oracle_unpack_b8.argtypes = [P, I64, P]
         lib.oracle_aggregate_w16.argtypes = [P, I64, I64, I64, ctypes.c_uint32, P]
@@ -152,6 +154,29 @@ def dft_complex(x: np.ndarray, N: int) -> np.ndarray:
     X = np.zeros((N, n_in, nb, 2), dtype=np.float64)
     if X.size:
         _load().oracle_dft_complex(_ptr(x), N, n_in, nb, _ptr(X))
+    return X
+
+
+def pfb_coeffs(P: int, N: int) -> np.ndarray:
+    """Prototype filter h[m], m < P*N: Hamming window times sinc((m - (PN-1)/2)/N)."""
+    h = np.zeros(P * N, dtype=np.float64)
+    _load().oracle_pfb_coeffs(P, N, _ptr(h))
+    return h
+
+
+def pfb_real(v: np.ndarray, N: int, P: int, h: np.ndarray | None = None, n_keep: int | None = None) -> np.ndarray:
+    """v: int8 [(n_blocks + P - 1)*N][n_in] -> FP64 [n_keep][n_in][n_blocks][2]: the real DFT of
+    y_b[n] = sum_p h[pN + n] v[(b + p)N + n] (h defaults to pfb_coeffs(P, N))."""
+    v = np.ascontiguousarray(v, dtype=np.int8)
+    ns, n_in = v.shape
+    assert ns % N == 0 and ns // N >= P
+    nb = ns // N - (P - 1)
+    h = pfb_coeffs(P, N) if h is None else np.ascontiguousarray(h, dtype=np.float64)
+    assert h.shape == (P * N,)
+    n_keep = N // 2 if n_keep is None else n_keep
+    X = np.zeros((n_keep, n_in, nb, 2), dtype=np.float64)
+    if X.size:
+        _load().oracle_pfb_real(_ptr(v), _ptr(h), N, P, n_in, nb, n_keep, _ptr(X))
     return X
 
 

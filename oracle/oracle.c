@@ -26,6 +26,14 @@
  *   oracle_requant
  *       Requantiser of the F-stage output (not in the paper, which correlates
  *       floats): q = clip(round_half_even(s*y), -max_abs, max_abs).
+ *   oracle_pfb_coeffs / oracle_pfb_real
+ *       Sec. 6.1 (further work): a polyphase filterbank in place of the plain
+ *       FFT, to cut the leakage of signals between channel centres.  The
+ *       paper gives no design; read here as the critically sampled
+ *       weighted-overlap-add form with P taps of N points: y_b[n] =
+ *       sum_{p<P} h[pN + n] x[(b + p)N + n], then the same real DFT as
+ *       oracle_dft_real.  Prototype filter h[m] = w[m] sinc((m - (PN-1)/2)/N),
+ *       Hamming window w[m] = 0.54 - 0.46 cos(2 pi m / (PN - 1)), m < PN.
  *   oracle_unpack_w16 / oracle_unpack_b8
  *       Sec. 3: a recorded sample has 5-bit real and 5-bit imaginary parts in
  *       two's complement, stored in a 16-bit word; Sec. 5's "1-byte" mode
@@ -178,6 +186,63 @@ void oracle_dft_real(const int8_t *v, int64_t N, int64_t n_in, int64_t n_blocks,
                 dst[1] = im;
             }
         }
+    }
+    free(cs);
+    free(sn);
+}
+
+/* h: double [P*N] prototype filter (see the header). */
+void oracle_pfb_coeffs(int64_t P, int64_t N, double *h)
+{
+    const double pi = 3.14159265358979323846264338327950288;
+    const int64_t L = P * N;
+    for (int64_t m = 0; m < L; ++m) {
+        const double w = (L > 1) ? 0.54 - 0.46 * cos(2.0 * pi * (double)m / (double)(L - 1)) : 1.0;
+        const double x = ((double)m - 0.5 * (double)(L - 1)) / (double)N;
+        const double sinc = (x == 0.0) ? 1.0 : sin(pi * x) / (pi * x);
+        h[m] = w * sinc;
+    }
+}
+
+/* v: int8 [(n_blocks + P - 1)*N][n_in] time-major; h: double [P*N].
+ * X: double [n_keep][n_in][n_blocks][2], the real DFT of y_b (see the header). */
+void oracle_pfb_real(const int8_t *v, const double *h, int64_t N, int64_t P, int64_t n_in, int64_t n_blocks,
+                     int64_t n_keep, double *X)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    if (N <= 0 || P <= 0) return;
+    double *cs = (double *)malloc((size_t)N * sizeof(double));
+    double *sn = (double *)malloc((size_t)N * sizeof(double));
+    if (!cs || !sn) { free(cs); free(sn); return; }
+    for (int64_t m = 0; m < N; ++m) {
+        cs[m] = cos(two_pi * (double)m / (double)N);
+        sn[m] = sin(two_pi * (double)m / (double)N);
+    }
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (i = 0; i < n_in; ++i) {
+        double *y = (double *)malloc((size_t)N * sizeof(double));
+        if (!y) continue;
+        for (int64_t b = 0; b < n_blocks; ++b) {
+            for (int64_t n = 0; n < N; ++n) {
+                double acc = 0.0;
+                for (int64_t p = 0; p < P; ++p)
+                    acc += h[p * N + n] * (double)v[((b + p) * N + n) * n_in + i];
+                y[n] = acc;
+            }
+            for (int64_t k = 0; k < n_keep; ++k) {
+                double re = 0.0, im = 0.0;
+                for (int64_t n = 0; n < N; ++n) {
+                    const int64_t m = (k * n) % N;
+                    re += y[n] * cs[m];
+                    im -= y[n] * sn[m];
+                }
+                double *dst = X + ((k * n_in + i) * n_blocks + b) * 2;
+                dst[0] = re;
+                dst[1] = im;
+            }
+        }
+        free(y);
     }
     free(cs);
     free(sn);
