@@ -116,7 +116,16 @@ typedef struct {
                                  F16/F8: conversion chunk in samples.        */
     int32_t volt_format;      /* corr_volt_t of corr_channelise's input (0
                                  when fft_size is 0)                         */
-    int32_t reserved;         /* must be 0                                   */
+    int32_t pfb_taps;         /* real F-stage only: 0 or 1 = plain DFT; P > 1
+                                 = polyphase filterbank of P taps (Sec. 6.1
+                                 suggests one against the DFT's leakage; this
+                                 build implements P = 4, other P return
+                                 CORR_E_UNSUPPORTED): block b's transform input
+                                 is y_b[n] = sum_{p<P} h[pN+n] x[(b+p)N+n],
+                                 h[m] = w[m] sinc((m - (PN-1)/2)/N) with the
+                                 Hamming window w[m] = 0.54 - 0.46 cos(2 pi m
+                                 / (PN-1)), N = fft_size, m < PN; 0 when
+                                 fft_size is 0                               */
 } corr_config;
 
 /* Bytes of device workspace a plan needs for `cfg`.  Host only. */
@@ -143,7 +152,11 @@ corr_status corr_destroy(corr_plan *plan);
  * transformed by a DFT (forward sign, unnormalised, no window).  Real input:
  * channels k = 0..fft_size/2-1 are kept (DC kept, Nyquist dropped).  Complex
  * input (Sec. 2: N_C samples give N_C channels): every k = 0..fft_size-1, in
- * natural order (DC first, negative frequencies in the upper half).  The
+ * natural order (DC first, negative frequencies in the upper half).  With
+ * cfg.pfb_taps = P > 1, d_volt holds n_blocks + P - 1 blocks (the caller
+ * repeats the last P - 1 blocks of one call at the start of the next) and
+ * spectrum b is that of y_b (see corr_config.pfb_taps); n_blocks counts the
+ * spectra.  The
  * spectra are scaled by requant_scale, rounded half to even, clipped to
  * +-max_abs and appended as one CI8 time sample per block to the ring
  * [n_channels][n_inputs][.] in the workspace.

@@ -32,7 +32,8 @@ VOLT_FORMATS = {"r8": 0, "cw16": 1, "cb8": 2}
 
 def make_config(n_inputs: int, n_channels: int, engine: str = "i8", sample_type: str = "ci8",
                 fft_size: int = 0, max_abs: int = 7, requant_scale: float = 0.0,
-                ring_samples: int = 0, fp64_longrun: bool = False, volt_format: str = "r8") -> corr_config:
+                ring_samples: int = 0, fp64_longrun: bool = False, volt_format: str = "r8",
+                pfb_taps: int = 0) -> corr_config:
     c = corr_config()
     c.n_inputs = n_inputs
     c.n_channels = n_channels
@@ -44,6 +45,7 @@ def make_config(n_inputs: int, n_channels: int, engine: str = "i8", sample_type:
     c.fp64_longrun = int(bool(fp64_longrun))
     c.ring_samples = ring_samples
     c.volt_format = VOLT_FORMATS[volt_format]
+    c.pfb_taps = pfb_taps
     return c
 
 
@@ -98,7 +100,8 @@ class Correlator:
 
     def __init__(self, n_inputs: int, n_channels: int, engine: str = "i8", sample_type: str = "ci8",
                  fft_size: int = 0, max_abs: int = 7, requant_scale: float = 0.0, ring_samples: int = 0,
-                 fp64_longrun: bool = False, device: str = "cuda:0", volt_format: str = "r8"):
+                 fp64_longrun: bool = False, device: str = "cuda:0", volt_format: str = "r8",
+                 pfb_taps: int = 0):
         import torch
 
         self._torch = torch
@@ -107,7 +110,7 @@ class Correlator:
         self.n_channels = n_channels
         self.engine = engine
         self.cfg = make_config(n_inputs, n_channels, engine, sample_type, fft_size, max_abs,
-                               requant_scale, ring_samples, fp64_longrun, volt_format)
+                               requant_scale, ring_samples, fp64_longrun, volt_format, pfb_taps)
         self.volt_format = volt_format
         self.ws_bytes = corr_workspace_bytes(self.cfg)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
@@ -120,7 +123,8 @@ class Correlator:
         t = self._torch
         want = {"r8": (t.int8,), "cw16": (t.int16, t.uint16), "cb8": (t.uint8, t.int8)}[self.volt_format]
         assert volt.dtype in want and volt.is_contiguous() and volt.device == self.device
-        n_blocks = volt.shape[0] // self.cfg.fft_size
+        # with a filterbank of P taps the input carries P - 1 blocks of history
+        n_blocks = volt.shape[0] // self.cfg.fft_size - max(0, self.cfg.pfb_taps - 1)
         dbg = 0
         if spectra_dbg is not None:
             assert spectra_dbg.dtype == t.float32 and spectra_dbg.is_contiguous()

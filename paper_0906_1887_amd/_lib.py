@@ -52,7 +52,7 @@ class corr_config(ctypes.Structure):
         ("fp64_longrun", ctypes.c_int32),
         ("ring_samples", ctypes.c_int64),
         ("volt_format", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("pfb_taps", ctypes.c_int32),
     ]
 
 

@@ -38,6 +38,7 @@ struct Layout {
   size_t ring = 0, ring_bytes = 0;
   size_t part = 0, part_bytes = 0;
   size_t tw = 0, tw_bytes = 0;
+  size_t pfb = 0, pfb_bytes = 0;       // filterbank coefficients (pfb_taps > 1)
   size_t stage = 0, stage_bytes = 0;   // FP16/FP8 staged samples
   size_t mbits = 0, scales = 0;        // FP8 per-channel max and 1/s^2
   int64_t stage_stride = 0;            // staged samples per row
@@ -68,8 +69,10 @@ corr_status validate(const corr_config* c) {
     if (c->sample_type != CORR_CI8 && c->fft_size == 0) return CORR_E_INVAL;
     if (c->max_abs < 1) return CORR_E_INVAL;  // int32 bound needs a declared range
   }
-  if (c->reserved != 0) return CORR_E_INVAL;
-  if (c->fft_size == 0 && c->volt_format != CORR_VOLT_R8) return CORR_E_INVAL;
+  if (c->pfb_taps < 0) return CORR_E_INVAL;
+  if (c->fft_size == 0 && (c->volt_format != CORR_VOLT_R8 || c->pfb_taps != 0)) return CORR_E_INVAL;
+  if (c->pfb_taps > 1 && c->volt_format != CORR_VOLT_R8) return CORR_E_UNSUPPORTED;
+  if (c->pfb_taps > 1 && c->pfb_taps != 4) return CORR_E_UNSUPPORTED;
   if (c->fft_size != 0) {
     if (c->volt_format == CORR_VOLT_R8) {
       if (c->fft_size != 2 * c->n_channels) return CORR_E_INVAL;
@@ -116,6 +119,11 @@ Layout layout_of(const corr_config* c) {
     L.tw = off;
     L.tw_bytes = (size_t)c->fft_size * sizeof(float2);
     off = align_up(off + L.tw_bytes, kAlign);
+    if (c->pfb_taps > 1) {
+      L.pfb = off;
+      L.pfb_bytes = (size_t)c->pfb_taps * c->fft_size * sizeof(float);
+      off = align_up(off + L.pfb_bytes, kAlign);
+    }
   }
   if (c->engine == CORR_X_F16 || c->engine == CORR_X_F8) {
     L.stage_sb = (c->engine == CORR_X_F16) ? 4 : 2;
@@ -145,6 +153,7 @@ struct corr_plan {
   hipStream_t stream;
   uint8_t* ws;
   std::vector<float2> tw_host;
+  std::vector<float> pfb_host;   // filterbank coefficients (kept for the asynchronous upload)
   int64_t n_accum = 0;       // samples in the integration accumulator
   bool acc_zero = true;      // accumulator logically zero (contents stale)
   bool error = false;
@@ -279,6 +288,18 @@ corr_status corr_create(const corr_config* cfg, void* d_workspace, size_t ws_byt
         p->tw_host[m] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
       }
       e = hipMemcpyAsync(at(p, L.tw), p->tw_host.data(), N * sizeof(float2), hipMemcpyHostToDevice, p->stream);
+      if (e == hipSuccess && cfg->pfb_taps > 1) {
+        // Prototype filter: Hamming window times sinc((m - (PN-1)/2)/N), in FP64, stored as float.
+        const int64_t len = (int64_t)cfg->pfb_taps * N;
+        p->pfb_host.resize(len);
+        for (int64_t m = 0; m < len; ++m) {
+          const double w = 0.54 - 0.46 * std::cos(2.0 * M_PI * (double)m / (double)(len - 1));
+          const double x = ((double)m - 0.5 * (double)(len - 1)) / (double)N;
+          const double sinc = (x == 0.0) ? 1.0 : std::sin(M_PI * x) / (M_PI * x);
+          p->pfb_host[m] = (float)(w * sinc);
+        }
+        e = hipMemcpyAsync(at(p, L.pfb), p->pfb_host.data(), len * sizeof(float), hipMemcpyHostToDevice, p->stream);
+      }
     }
     if (e != hipSuccess) {
       delete p;
@@ -350,6 +371,8 @@ corr_status corr_channelise(corr_plan* p, const void* d_volt, int64_t n_blocks, 
       fc.scale = c.requant_scale;
       fc.max_abs = (float)c.max_abs;
       fc.format = c.volt_format;
+      fc.pfb_taps = c.pfb_taps;
+      fc.pfb = c.pfb_taps > 1 ? static_cast<const float*>(at(p, p->L.pfb)) : nullptr;
       const hipError_t e = (c.volt_format == CORR_VOLT_R8) ? corr::launch_fstage_call(fc, p->stream)
                                                           : corr::launch_fstage_complex(fc, p->stream);
       if (e != hipSuccess) return hip_fail(p, e);

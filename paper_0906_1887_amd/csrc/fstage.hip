@@ -41,6 +41,7 @@ struct FArgs {
   int32_t vec_out;         // 1: t_offset % 8 == 0 and ring_stride % 8 == 0
   int64_t n_items;         // block groups x input groups
   int64_t per_xcd;         // ceil(n_items / 8)
+  const float* pfb;        // filterbank coefficients h[p*256 + n], p < TAPS (TAPS > 1 only)
 };
 
 // Low bytes of four requantised values -> (b0, b1, b2, b3) of one word.
@@ -65,13 +66,22 @@ __device__ __forceinline__ float sbyte(uint32_t w) {
 // workgroup's corner turn for the current pair.
 constexpr int kORow = 20;  // words per channel row of O (16 blocks + pad, 16-byte aligned rows)
 
-template <int IN>
-__global__ __launch_bounds__(256, 3) void fstage_kernel(FArgs a) {
+//
+// TAPS > 1: polyphase filterbank in place of the plain transform (Sec. 6.1
+// names it as the cure for the FFT's leakage): the input holds TAPS - 1
+// more blocks than there are outputs, and block b's transform input is
+// y_b[n] = sum_p h[p*256 + n] x[(b + p)*256 + n] (weighted overlap-add of
+// TAPS consecutive blocks), formed in the unpack from registers that hold
+// all TAPS blocks of the slot's samples (8 inputs per workgroup).
+template <int IN, int TAPS>
+__global__ __launch_bounds__(256, (TAPS > 1 ? 2 : 3)) void fstage_kernel(FArgs a) {
   static_assert(IN == 8 || IN == 16, "inputs per workgroup");
+  static_assert(TAPS == 1 || IN == 8, "the filterbank path takes 8 inputs per workgroup");
   constexpr int kW = IN / 4;  // words per sample and lane
   __shared__ __attribute__((aligned(16))) float2 S[kFFtPerRound][kFSRow * 16];  // 34 KB
   __shared__ __attribute__((aligned(16))) uint32_t O[kFCh][kORow];              // 10 KB
   __shared__ float2 tw[kFN];                                                     // 2 KB
+  __shared__ float hs[TAPS > 1 ? TAPS * kFN : 1];                                // filterbank: 1 KB per tap
 
   const int tid = threadIdx.x;
   // The n_ig workgroups of one block group read the same input rows; the
@@ -85,40 +95,48 @@ __global__ __launch_bounds__(256, 3) void fstage_kernel(FArgs a) {
   const int l = tid & 15;  // lane within the FFT
   const int64_t nb = min((int64_t)kFBlk, a.n_blocks - b0);
 
-  // Samples t = l + 16 n2 of block b0 + f, inputs i0..i0+IN-1 (zero outside).
-  uint32_t w[16][kW];
-  if (a.vec_in && nb == kFBlk) {
-    const int8_t* p = a.volt + ((b0 + f) * kFN + l) * a.n_in + i0;
+  // Samples t = l + 16 n2 of blocks b0 + f + tp (tp < TAPS), inputs
+  // i0..i0+IN-1 (zero outside).
+  uint32_t w[TAPS][16][kW];
 #pragma unroll
-    for (int n2 = 0; n2 < 16; ++n2) {
-      const int8_t* q = p + (int64_t)n2 * 16 * a.n_in;
-      if constexpr (IN == 16) {
-        const uint4 v = *reinterpret_cast<const uint4*>(q);
-        w[n2][0] = v.x; w[n2][1] = v.y; w[n2][2] = v.z; w[n2][3] = v.w;
-      } else {
-        const uint2 v = *reinterpret_cast<const uint2*>(q);
-        w[n2][0] = v.x; w[n2][1] = v.y;
-      }
-    }
-  } else {
+  for (int tp = 0; tp < TAPS; ++tp) {
+    if (a.vec_in && nb == kFBlk) {
+      const int8_t* p = a.volt + ((b0 + f + tp) * kFN + l) * a.n_in + i0;
 #pragma unroll
-    for (int n2 = 0; n2 < 16; ++n2) {
-      const int64_t t = (b0 + f) * kFN + l + 16 * n2;
-      const int8_t* p = a.volt + t * a.n_in + i0;
-#pragma unroll
-      for (int j = 0; j < kW; ++j) {
-        uint32_t v = 0;
-        for (int q = 0; q < 4; ++q) {
-          const int i = 4 * j + q;
-          if (f < nb && i0 + i < a.n_in) v |= (uint32_t)(uint8_t)p[i] << (8 * q);
+      for (int n2 = 0; n2 < 16; ++n2) {
+        const int8_t* q = p + (int64_t)n2 * 16 * a.n_in;
+        if constexpr (IN == 16) {
+          const uint4 v = *reinterpret_cast<const uint4*>(q);
+          w[tp][n2][0] = v.x; w[tp][n2][1] = v.y; w[tp][n2][2] = v.z; w[tp][n2][3] = v.w;
+        } else {
+          const uint2 v = *reinterpret_cast<const uint2*>(q);
+          w[tp][n2][0] = v.x; w[tp][n2][1] = v.y;
         }
-        w[n2][j] = v;
+      }
+    } else {
+#pragma unroll
+      for (int n2 = 0; n2 < 16; ++n2) {
+        const int64_t t = (b0 + f + tp) * kFN + l + 16 * n2;
+        const int8_t* p = a.volt + t * a.n_in + i0;
+#pragma unroll
+        for (int j = 0; j < kW; ++j) {
+          uint32_t v = 0;
+          for (int q = 0; q < 4; ++q) {
+            const int i = 4 * j + q;
+            if (f < nb && i0 + i < a.n_in) v |= (uint32_t)(uint8_t)p[i] << (8 * q);
+          }
+          w[tp][n2][j] = v;
+        }
       }
     }
   }
   // Twiddle table W_256^m; a lane reads W_256^(l k2) for every round from it
   // (the first round's barrier orders these writes before the first read).
   tw[tid] = a.twiddle[tid];
+  if constexpr (TAPS > 1) {
+    for (int m = tid; m < TAPS * kFN; m += 256) hs[m] = a.pfb[m];
+    __syncthreads();  // the unpack of the first round reads hs
+  }
 
   const float h = 0.5f * a.scale;  // the 1/2 of the two-for-one split folded into the scale
   const float lo = kRqMagic - a.max_abs, hi = kRqMagic + a.max_abs;
@@ -138,11 +156,24 @@ __global__ __launch_bounds__(256, 3) void fstage_kernel(FArgs a) {
       float2 x[16], X[16];
 #pragma unroll
       for (int n2 = 0; n2 < 16; ++n2) {
-        const uint32_t d = w[n2][r >> 1];
-        if (r & 1)
-          x[n2] = make_float2(sbyte<2>(d), sbyte<3>(d));
-        else
-          x[n2] = make_float2(sbyte<0>(d), sbyte<1>(d));
+        if constexpr (TAPS == 1) {
+          const uint32_t d = w[0][n2][r >> 1];
+          if (r & 1)
+            x[n2] = make_float2(sbyte<2>(d), sbyte<3>(d));
+          else
+            x[n2] = make_float2(sbyte<0>(d), sbyte<1>(d));
+        } else {
+          const int n = l + 16 * n2;
+          float xr = 0.f, xi = 0.f;
+#pragma unroll
+          for (int tp = 0; tp < TAPS; ++tp) {
+            const uint32_t d = w[tp][n2][r >> 1];
+            const float hv = hs[tp * kFN + n];
+            xr = fmaf(hv, (r & 1) ? sbyte<2>(d) : sbyte<0>(d), xr);
+            xi = fmaf(hv, (r & 1) ? sbyte<3>(d) : sbyte<1>(d), xi);
+          }
+          x[n2] = make_float2(xr, xi);
+        }
       }
       dft16(x, X);
       if (pr == 0) __syncthreads();  // tw is complete
@@ -213,16 +244,18 @@ __global__ __launch_bounds__(256, 3) void fstage_kernel(FArgs a) {
     if constexpr (IN == 16) {
 #pragma unroll
       for (int n2 = 0; n2 < 16; ++n2) {
-        w[n2][0] = w[n2][2];
-        w[n2][1] = w[n2][3];
+        w[0][n2][0] = w[0][n2][2];
+        w[0][n2][1] = w[0][n2][3];
       }
     }
   }
 }
 
-// 16 inputs per workgroup when n_in is a multiple of 16, else 8.
-hipError_t launch_fstage(const FArgs& a, hipStream_t s) {
-  const int in = (a.n_in % 16 == 0) ? 16 : 8;
+// 16 inputs per workgroup when n_in is a multiple of 16 (plain transform),
+// else 8; the filterbank path (taps > 1, this build: 4) takes 8.
+hipError_t launch_fstage(const FArgs& a, int taps, hipStream_t s) {
+  if (taps != 1 && taps != 4) return hipErrorInvalidValue;
+  const int in = (taps == 1 && a.n_in % 16 == 0) ? 16 : 8;
   const int64_t n_bg = (a.n_blocks + kFBlk - 1) / kFBlk;
   FArgs b = a;
   b.n_ig = (a.n_in + in - 1) / in;
@@ -232,10 +265,12 @@ hipError_t launch_fstage(const FArgs& a, hipStream_t s) {
   b.per_xcd = (b.n_items + kNumXcd - 1) / kNumXcd;
   const int64_t grid = b.per_xcd * kNumXcd;
   if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
-  if (in == 16)
-    hipLaunchKernelGGL(fstage_kernel<16>, dim3((unsigned)grid), dim3(256), 0, s, b);
+  if (taps == 4)
+    hipLaunchKernelGGL((fstage_kernel<8, 4>), dim3((unsigned)grid), dim3(256), 0, s, b);
+  else if (in == 16)
+    hipLaunchKernelGGL((fstage_kernel<16, 1>), dim3((unsigned)grid), dim3(256), 0, s, b);
   else
-    hipLaunchKernelGGL(fstage_kernel<8>, dim3((unsigned)grid), dim3(256), 0, s, b);
+    hipLaunchKernelGGL((fstage_kernel<8, 1>), dim3((unsigned)grid), dim3(256), 0, s, b);
   return hipGetLastError();
 }
 
@@ -256,7 +291,8 @@ hipError_t launch_fstage_call(const FStageCall& c, hipStream_t s) {
   a.scale = c.scale;
   a.max_abs = c.max_abs;
   a.vec_out = (c.t_offset % 8 == 0) && (c.ring_stride % 8 == 0) && ((reinterpret_cast<uintptr_t>(c.ring) & 15) == 0);
-  return launch_fstage(a, s);
+  a.pfb = c.pfb;
+  return launch_fstage(a, c.pfb_taps > 1 ? c.pfb_taps : 1, s);
 }
 
 }  // namespace corr

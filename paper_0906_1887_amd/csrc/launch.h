@@ -32,6 +32,8 @@ struct FStageCall {
   float scale;
   float max_abs;
   int32_t format;          // 0: real 256-point F-stage; 1, 2: complex 128-point F-stage
+  int32_t pfb_taps;        // real F-stage: > 1 = polyphase filterbank taps (volt holds taps - 1 more blocks)
+  const float* pfb;        // filterbank coefficients [pfb_taps * 256]
 };
 hipError_t launch_fstage_call(const FStageCall& c, hipStream_t s);
 hipError_t launch_fstage_complex(const FStageCall& c, hipStream_t s);

@@ -390,3 +390,14 @@ def complex_bytes(seed: int, index: int, n_samples: int, n_inputs: int, **kw):
     lv = complex_levels(seed, index, n_samples, n_inputs, bits=4, **kw)
     b = (((lv[..., 0].astype(np.int64) & 15) << 4) | (lv[..., 1].astype(np.int64) & 15)).astype(np.uint8)
     return b, lv
+
+
+def real_tone(seed: int, n_samples: int, n_inputs: int, bin_pos: float, amp: float = 60.0,
+              sigma: float = 1.0, fft_size: int = 256) -> np.ndarray:
+    """int8 [n_samples][n_inputs]: rint(amp cos(2 pi bin_pos t / fft_size) + sigma n), a tone
+    continuous across blocks (any bin position, also between channel centres) over
+    Gaussian noise (numpy PCG64)."""
+    rng = np.random.default_rng([seed, 0x70E])
+    t = np.arange(n_samples, dtype=np.float64)
+    v = amp * np.cos(2.0 * np.pi * bin_pos * t / fft_size)[:, None] + sigma * rng.standard_normal((n_samples, n_inputs))
+    return np.clip(np.rint(v), -128, 127).astype(np.int8)
