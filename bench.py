@@ -406,7 +406,34 @@ def c2_config(dev, stream, reps=20):
                     "note": "per integration of 10000 blocks x 64 inputs; algorithmic bytes: F 1 B in + 2 B out "
                             "per sample, X 2 B per sample in + 8 B per product out"}
     c.close()
-    del volt
+    # the polyphase-filterbank F-stage (4 taps) on the same data, 3 blocks of history added
+    vp = torch.cat([volt[: 3 * 256], volt]).contiguous()
+    c = Correlator(n_in, 128, engine="i8", fft_size=256, max_abs=7, requant_scale=s_req, ring_samples=nb,
+                   device=str(dev), pfb_taps=4)
+    sq = [0]
+
+    def fp():
+        c.channelise(vp, first_seq=sq[0])
+        sq[0] += nb
+        c.correlate(None)
+        c.dump(0)
+    fp()
+    pf = 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        c.channelise(vp, first_seq=sq[0])
+        e1.record(stream)
+        sq[0] += nb
+        c.correlate(None)
+        c.dump(0)
+        torch.cuda.synchronize()
+        pf += e0.elapsed_time(e1)
+    pf /= reps
+    c.close()
+    out["c2_fx"]["fstage_pfb4_ms"] = pf
+    out["c2_fx"]["fstage_pfb4_frac_of_hbm"] = f_bytes / (pf / 1e3) / hbm
+    del volt, vp
     return out
 
 
