@@ -47,9 +47,9 @@ __global__ __launch_bounds__(256) void aggregate_w16_kernel(const uint16_t* __re
 
 // The prototype's layout (16 words per record, up to 4 streams): a workgroup
 // copies 256 records of every stream into LDS with contiguous dword loads
-// (256 records x 34 bytes is a whole number of dwords), then thread r packs
-// record r of every stream into its output row (whole 16-byte stores) and
-// checks the counters.
+// (256 records x 34 bytes is a whole number of dwords), then writes its
+// output rows as one contiguous run of 16-byte pieces and checks the
+// counters.
 constexpr int kAggRec = 256;
 constexpr int kAggWords = 17;  // marker + 16 samples
 __global__ __launch_bounds__(256) void aggregate_w16_rows_kernel(const uint16_t* __restrict__ rec, int32_t n_streams,
@@ -66,19 +66,27 @@ __global__ __launch_bounds__(256) void aggregate_w16_rows_kernel(const uint16_t*
     for (int d = tid; d < nd; d += 256) buf[s][d] = src[d];
   }
   __syncthreads();
+  // Output: the workgroup's rows are one contiguous run of nr * n_streams * 32
+  // bytes; 16-byte piece p holds half (p % 2) of stream (p / 2 % n_streams)'s
+  // samples of record p / (2 n_streams), so each store instruction writes
+  // 1 KB in one run.
+  const int pieces = nr * n_streams * 2;
+  uint4* dst = reinterpret_cast<uint4*>(out + r0 * (int64_t)n_streams * 16);
+  for (int pc = tid; pc < pieces; pc += 256) {
+    const int r = pc / (2 * n_streams);
+    const int s = (pc >> 1) - r * n_streams;
+    const uint16_t* b = reinterpret_cast<const uint16_t*>(buf[s]) + r * kAggWords + 1 + 8 * (pc & 1);
+    uint32_t wd[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wd[q] = (uint32_t)b[2 * q] | ((uint32_t)b[2 * q + 1] << 16);
+    dst[pc] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+  }
+  // Counters: thread r checks record r of every stream.
   if (tid >= nr) return;
   const uint16_t want = (uint16_t)((first_counter + (uint64_t)(r0 + tid)) & 0xFFFFu);
   bool mismatch = false;
-  uint4* dst = reinterpret_cast<uint4*>(out + (r0 + tid) * (int64_t)n_streams * 16);
-  for (int s = 0; s < n_streams; ++s) {
-    const uint16_t* b = reinterpret_cast<const uint16_t*>(buf[s]) + tid * kAggWords;
-    mismatch |= (b[0] != want);
-    uint32_t wd[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) wd[q] = (uint32_t)b[1 + 2 * q] | ((uint32_t)b[2 + 2 * q] << 16);
-    dst[2 * s] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
-    dst[2 * s + 1] = make_uint4(wd[4], wd[5], wd[6], wd[7]);
-  }
+  for (int s = 0; s < n_streams; ++s)
+    mismatch |= (reinterpret_cast<const uint16_t*>(buf[s])[tid * kAggWords] != want);
   if (mismatch && bad != nullptr) atomicAdd(bad, 1u);
 }
 
