@@ -66,6 +66,65 @@ def test_workspace_and_validation():
         assert e.value.status == _lib.CORR_E_UNSUPPORTED, kw
 
 
+def test_front_end_and_filterbank_validation():
+    """The complex front end (volt_format) and the filterbank (pfb_taps)."""
+    from paper_0906_1887_amd import _lib
+    base = dict(n_inputs=64, n_channels=128, engine="i8", requant_scale=0.0625, ring_samples=100)
+    plain = _lib.corr_workspace_bytes(_cfg(fft_size=256, **base))
+    pfb = _lib.corr_workspace_bytes(_cfg(fft_size=256, pfb_taps=4, **base))
+    assert pfb >= plain + 4 * 256 * 4                    # the coefficient table
+    assert _lib.corr_workspace_bytes(_cfg(fft_size=128, volt_format="cw16", **base)) > 0
+    assert _lib.corr_workspace_bytes(_cfg(fft_size=128, volt_format="cb8", **base)) > 0
+    inval = [
+        dict(fft_size=256, volt_format="cw16", **base),    # complex: fft_size must equal n_channels
+        dict(fft_size=0, volt_format="cb8", **base),       # a format without an F-stage
+        dict(fft_size=0, pfb_taps=4, **base),              # a filterbank without an F-stage
+        dict(fft_size=256, pfb_taps=-1, **base),
+    ]
+    for kw in inval:
+        with pytest.raises(_lib.CorrError) as e:
+            _lib.corr_workspace_bytes(_cfg(**kw))
+        assert e.value.status == _lib.CORR_E_INVAL, kw
+    unsup = [
+        dict(fft_size=256, pfb_taps=3, **base),            # this build's filterbank has 4 taps
+        dict(fft_size=128, volt_format="cw16", pfb_taps=4, **base),   # the filterbank is real-input only
+        dict(n_inputs=8, n_channels=64, engine="i8", fft_size=64, volt_format="cb8", requant_scale=0.1,
+             ring_samples=10),                             # this build's complex DFT is 128 points
+    ]
+    for kw in unsup:
+        with pytest.raises(_lib.CorrError) as e:
+            _lib.corr_workspace_bytes(_cfg(**kw))
+        assert e.value.status == _lib.CORR_E_UNSUPPORTED, kw
+    c = _cfg(**base)
+    c.volt_format = 7
+    c.fft_size = 128
+    with pytest.raises(_lib.CorrError) as e:
+        _lib.corr_workspace_bytes(c)
+    assert e.value.status == _lib.CORR_E_INVAL
+
+
+def test_plan_free_entry_points_reject_bad_arguments():
+    """corr_aggregate_w16 and corr_cmac_design validate on the host before any
+    launch (null pointers are never dereferenced)."""
+    from paper_0906_1887_amd import _lib
+    for args in ((0, 1, 4, 16, 0, 0), (1, 0, 1, 16, 0, 0), (1, 4, 0, 16, 0, 0), (1, 4, 16, -1, 0, 0)):
+        d_rec, ns, wp, nr, c0, d_out = args
+        with pytest.raises(_lib.CorrError) as e:
+            _lib.corr_aggregate_w16(d_rec, ns, wp, nr, c0, d_out)
+        assert e.value.status == _lib.CORR_E_INVAL, args
+    for design, group, n_in, n_ch, T in ((3, 1, 8, 4, 1), (0, 2, 8, 4, 1), (1, 3, 8, 4, 1), (2, 4, 6, 4, 1),
+                                         (0, 1, 0, 4, 1), (0, 1, 8, 0, 1), (0, 1, 8, 4, -1)):
+        with pytest.raises(_lib.CorrError) as e:
+            _lib.corr_cmac_design(design, group, 0x1000, T, n_in, n_ch, 0x2000)
+        assert e.value.status == _lib.CORR_E_INVAL, (design, group, n_in, n_ch, T)
+    with pytest.raises(_lib.CorrError) as e:      # null spectra
+        _lib.corr_cmac_design(0, 1, 0, 1, 8, 4, 0x2000)
+    assert e.value.status == _lib.CORR_E_INVAL
+    with pytest.raises(_lib.CorrError) as e:      # beyond the 128-input pair table
+        _lib.corr_cmac_design(0, 1, 0x1000, 1, 130, 4, 0x2000)
+    assert e.value.status == _lib.CORR_E_UNSUPPORTED
+
+
 def test_create_rejects_bad_workspace():
     from paper_0906_1887_amd import _lib
     cfg = _cfg(n_inputs=16, n_channels=2, engine="i8")
