@@ -147,11 +147,11 @@ __device__ __forceinline__ float2 unpack_sample(uint32_t d, int shift) {
 }
 
 // One workgroup: 16 blocks x 8 inputs (16 bytes per time instant for 16-bit
-// words, 8 for bytes).  Slot f = tid / 8 (lanes
-// l = tid % 8) owns block f % 16 and, in round pr, input 2 pr + f / 16 (the
-// two inputs of a round sit in different waves); it loads its 16 samples
-// x IN inputs straight into registers.  S[f] is used by the 8 lanes of slot
-// f only, all in one wave; O is the workgroup's corner turn for the round.
+// words, 8 for bytes).  Slot f = tid / 8 (lanes l = tid % 8) owns block
+// f % 16 and, in round pr, input 2 pr + f / 16 (the two inputs of a round sit
+// in different waves); it loads its 16 samples x 8 inputs straight into
+// registers.  S[f] is used by the 8 lanes of slot f only, all in one wave; O
+// is the workgroup's corner turn for the round.
 template <int FMT>
 __global__ __launch_bounds__(256, 3) void fstage_c_kernel(CArgs a) {
   constexpr int SB = (FMT == 1) ? 2 : 1;  // bytes per sample
