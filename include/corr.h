@@ -205,7 +205,9 @@ corr_status corr_aggregate_w16(const uint16_t *d_records, int32_t n_streams, int
  * CORR_E_INVAL for an unknown design, a group not allowed for it, n_inputs not
  * a multiple of the group, n_inputs or n_channels < 1, n_samples < 0 or a
  * NULL buffer; CORR_E_UNSUPPORTED for n_inputs > 128.  No plan needed;
- * asynchronous on hip_stream (NULL = default stream). */
+ * asynchronous on hip_stream (NULL = default stream), except that the first
+ * call on a device uploads the 33 KB pair table to constant memory
+ * synchronously (so it must not be the first call inside a stream capture). */
 typedef enum {
     CORR_DESIGN_PP = 0,
     CORR_DESIGN_GP = 1,
