@@ -156,10 +156,9 @@ corr_status corr_destroy(corr_plan *plan);
  * cfg.pfb_taps = P > 1, d_volt holds n_blocks + P - 1 blocks (the caller
  * repeats the last P - 1 blocks of one call at the start of the next) and
  * spectrum b is that of y_b (see corr_config.pfb_taps); n_blocks counts the
- * spectra.  The
- * spectra are scaled by requant_scale, rounded half to even, clipped to
- * +-max_abs and appended as one CI8 time sample per block to the ring
- * [n_channels][n_inputs][.] in the workspace.
+ * spectra.  The spectra are scaled by requant_scale, rounded half to even,
+ * clipped to +-max_abs and appended as one CI8 time sample per block to the
+ * ring [n_channels][n_inputs][.] in the workspace.
  * first_seq: sequence number of the first block; it must equal the number
  * that follows the previous call's last block (any value on the first call
  * or after corr_seq_reset), else CORR_E_SEQ and nothing is done.
@@ -183,7 +182,7 @@ corr_status corr_channelise(corr_plan *plan, const void *d_volt, int64_t n_block
  * 2^16 in at least one stream; the data are copied regardless.  No plan
  * needed; asynchronous on hip_stream (NULL = default stream).
  * CORR_E_INVAL for n_streams or words_per_record < 1, n_records < 0, or a
- * NULL buffer with n_records > 0. */
+ * NULL buffer with n_records > 0; CORR_E_HIP if the launch fails. */
 corr_status corr_aggregate_w16(const uint16_t *d_records, int32_t n_streams, int32_t words_per_record,
                                int64_t n_records, uint32_t first_counter, uint16_t *d_out,
                                uint32_t *d_bad_records, void *hip_stream);
@@ -204,7 +203,8 @@ corr_status corr_aggregate_w16(const uint16_t *d_records, int32_t n_streams, int
  *     LDS used as register space (no barrier), redundant half exits.
  * CORR_E_INVAL for an unknown design, a group not allowed for it, n_inputs not
  * a multiple of the group, n_inputs or n_channels < 1, n_samples < 0 or a
- * NULL buffer; CORR_E_UNSUPPORTED for n_inputs > 128.  No plan needed;
+ * NULL buffer; CORR_E_UNSUPPORTED for n_inputs > 128; CORR_E_HIP if the
+ * table upload or the launch fails.  No plan needed;
  * asynchronous on hip_stream (NULL = default stream), except that the first
  * call on a device uploads the 33 KB pair table to constant memory
  * synchronously (so it must not be the first call inside a stream capture). */
