@@ -212,9 +212,10 @@ __global__ __launch_bounds__(256, 3) void fstage_c_kernel(CArgs a) {
   // One round per input pair.  This slot's sample of round pr sits in word 0
   // at bit 16 hi (16-bit words) or 8 hi (bytes); after a round the next pair
   // is brought there (words move down; for bytes, every other round shifts
-  // word 0 down by 16 bits instead).
+  // word 0 down by 16 bits instead).  Fully unrolled, those moves become
+  // register renames.
   const int shift = (FMT == 1) ? 16 * hi : 8 * hi;
-#pragma unroll 1
+#pragma unroll
   for (int pr = 0; pr < IN / 2; ++pr) {
     {
       float2 x[16], X[16];
