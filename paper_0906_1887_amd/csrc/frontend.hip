@@ -46,24 +46,42 @@ __global__ __launch_bounds__(256) void aggregate_w16_kernel(const uint16_t* __re
 }
 
 // The prototype's layout (16 words per record, up to 4 streams): a workgroup
-// copies 256 records of every stream into LDS with contiguous dword loads
-// (256 records x 34 bytes is a whole number of dwords), then writes its
-// output rows as one contiguous run of 16-byte pieces and checks the
-// counters.
-constexpr int kAggRec = 256;
-constexpr int kAggWords = 17;  // marker + 16 samples
+// copies 128 records of every stream into LDS (128 records x 34 bytes is a
+// whole number of 16-byte pieces; VEC loads 16 bytes per lane and needs every
+// stream's run 16-byte aligned, else dwords), then writes its output rows as
+// one contiguous run of 16-byte pieces and checks the counters.  Each piece
+// is five LDS dwords funnel-shifted by 0 or 16 bits, since a record's samples
+// start 2 bytes past its marker.  At 17.5 KB of LDS, eight workgroups fit
+// on a CU.
+constexpr int kAggRec = 128;
+constexpr int kAggWords = 17;                          // marker + 16 samples
+constexpr int kAggDw = kAggRec * kAggWords / 2;        // dwords per stream
+constexpr int kAggPitch = kAggDw + 8;                  // streams 8 banks apart
+static_assert(kAggDw % 4 == 0 && kAggPitch % 4 == 0, "16-byte LDS rows");
+template <bool VEC>
 __global__ __launch_bounds__(256) void aggregate_w16_rows_kernel(const uint16_t* __restrict__ rec, int32_t n_streams,
                                                                  int64_t n_rec, uint32_t first_counter,
                                                                  uint16_t* __restrict__ out,
                                                                  uint32_t* __restrict__ bad) {
-  __shared__ uint32_t buf[4][kAggRec * kAggWords / 2];  // 34 KB
+  __shared__ __align__(16) uint32_t buf[4 * kAggPitch];  // 17.5 KB; kAggPitch is a multiple of 4
   const int tid = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * kAggRec;
   const int nr = (int)min((int64_t)kAggRec, n_rec - r0);  // even: n_rec and r0 are
   const int nd = nr * kAggWords / 2;
-  for (int s = 0; s < n_streams; ++s) {
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(rec + ((int64_t)s * n_rec + r0) * kAggWords);
-    for (int d = tid; d < nd; d += 256) buf[s][d] = src[d];
+  // One flat loop over every stream's run keeps all lanes loading.
+  if (VEC) {
+    const int nq = nd / 4;   // nr is a multiple of 8 here, so nd is a multiple of 4
+    for (int d = tid; d < n_streams * nq; d += 256) {
+      const int s = d / nq, q = d - s * nq;
+      const uint4* src4 = reinterpret_cast<const uint4*>(rec + ((int64_t)s * n_rec + r0) * kAggWords);
+      reinterpret_cast<uint4*>(buf + s * kAggPitch)[q] = src4[q];
+    }
+  } else {
+    for (int d = tid; d < n_streams * nd; d += 256) {
+      const int s = d / nd, q = d - s * nd;
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(rec + ((int64_t)s * n_rec + r0) * kAggWords);
+      buf[s * kAggPitch + q] = src[q];
+    }
   }
   __syncthreads();
   // Output: the workgroup's rows are one contiguous run of nr * n_streams * 32
@@ -75,18 +93,22 @@ __global__ __launch_bounds__(256) void aggregate_w16_rows_kernel(const uint16_t*
   for (int pc = tid; pc < pieces; pc += 256) {
     const int r = pc / (2 * n_streams);
     const int s = (pc >> 1) - r * n_streams;
-    const uint16_t* b = reinterpret_cast<const uint16_t*>(buf[s]) + r * kAggWords + 1 + 8 * (pc & 1);
-    uint32_t wd[4];
+    const int o = r * (2 * kAggWords) + 2 + 16 * (pc & 1);   // byte offset of the piece in its stream
+    const uint32_t* b = buf + s * kAggPitch + (o >> 2);
+    const uint32_t sh = (uint32_t)(o & 3) * 8;                 // 0 or 16
+    uint32_t w[5];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) wd[q] = (uint32_t)b[2 * q] | ((uint32_t)b[2 * q + 1] << 16);
-    dst[pc] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+    for (int q = 0; q < 4; ++q) w[q] = b[q];
+    w[4] = sh ? b[4] : 0u;                                     // b[4] lies inside the record when sh != 0
+    dst[pc] = make_uint4(__builtin_amdgcn_alignbit(w[1], w[0], sh), __builtin_amdgcn_alignbit(w[2], w[1], sh),
+                         __builtin_amdgcn_alignbit(w[3], w[2], sh), __builtin_amdgcn_alignbit(w[4], w[3], sh));
   }
   // Counters: thread r checks record r of every stream.
   if (tid >= nr) return;
   const uint16_t want = (uint16_t)((first_counter + (uint64_t)(r0 + tid)) & 0xFFFFu);
   bool mismatch = false;
   for (int s = 0; s < n_streams; ++s)
-    mismatch |= (reinterpret_cast<const uint16_t*>(buf[s])[tid * kAggWords] != want);
+    mismatch |= (reinterpret_cast<const uint16_t*>(buf + s * kAggPitch)[tid * kAggWords] != want);
   if (mismatch && bad != nullptr) atomicAdd(bad, 1u);
 }
 
@@ -98,8 +120,14 @@ hipError_t launch_aggregate_w16(const uint16_t* rec, int32_t n_streams, int32_t 
       (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
     const int64_t grid = (n_rec + kAggRec - 1) / kAggRec;
     if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(aggregate_w16_rows_kernel, dim3((unsigned)grid), dim3(256), 0, s, rec, n_streams, n_rec,
-                       first_counter, out, bad);
+    // 16-byte loads: every stream's run of kAggRec records starts 16-byte aligned.
+    const bool vec = (reinterpret_cast<uintptr_t>(rec) & 15) == 0 && n_rec % 8 == 0;
+    if (vec)
+      hipLaunchKernelGGL(aggregate_w16_rows_kernel<true>, dim3((unsigned)grid), dim3(256), 0, s, rec, n_streams,
+                         n_rec, first_counter, out, bad);
+    else
+      hipLaunchKernelGGL(aggregate_w16_rows_kernel<false>, dim3((unsigned)grid), dim3(256), 0, s, rec, n_streams,
+                         n_rec, first_counter, out, bad);
     return hipGetLastError();
   }
   const int64_t grid = (total + 255) / 256;

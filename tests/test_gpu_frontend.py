@@ -46,7 +46,10 @@ def check(levels, dbg, q_gpu, n_in):
 
 
 def test_aggregate_bit_exact_and_counters():
-    for ns, nr, wp, c0 in ((4, 3000, 16, 65000), (3, 77, 5, 0), (1, 1, 1, 9)):
+    # 16-word records: 16-byte loads (record count a multiple of 8; a ragged
+    # last workgroup of 184 records) and dword loads (1282 records: 2 in the
+    # last workgroup); then the generic kernel.
+    for ns, nr, wp, c0 in ((4, 3000, 16, 65000), (4, 1282, 16, 7), (2, 512, 16, 0), (3, 77, 5, 0), (1, 1, 1, 9)):
         say(f"[aggregate] streams={ns} records={nr} words={wp}")
         rec, _ = synth.capture_records(seed=3, index=nr, n_records=nr, n_streams=ns, w_per=wp, first_counter=c0)
         want, bad = oracle.aggregate_w16(rec, c0)
