@@ -192,8 +192,13 @@ __global__ __launch_bounds__(256, 3) void fstage_c_kernel(CArgs a) {
   const int tid = threadIdx.x;
   const int64_t item = xcd_item(blockIdx.x, a.per_xcd);
   if ((int64_t)(blockIdx.x / kNumXcd) >= a.per_xcd || item >= a.n_items) return;
-  const int ig = (int)(item % a.n_ig);
-  const int64_t b0 = (item / a.n_ig) * kCBlk;
+  // Items run through 4 consecutive block groups of one input group (the
+  // four 32-byte pieces of each 128-byte ring line), then input groups, then
+  // the next 4 block groups.
+  const int64_t rest = item >> 2;
+  const int ig = (int)(rest % a.n_ig);
+  const int64_t b0 = ((rest / a.n_ig) * 4 + (item & 3)) * kCBlk;
+  if (b0 >= a.n_blocks) return;
   const int i0 = ig * IN;
   const int f = tid >> 3;
   const int l = tid & 7;
@@ -336,7 +341,7 @@ hipError_t launch_fstage_complex(const FStageCall& c, hipStream_t s) {
   a.vec_in = (c.n_in % in == 0) && ((reinterpret_cast<uintptr_t>(c.volt) & (in * sb - 1)) == 0);
   a.vec_out = (c.t_offset % 8 == 0) && (c.ring_stride % 8 == 0) && ((reinterpret_cast<uintptr_t>(c.ring) & 15) == 0);
   const int64_t n_bg = (c.n_blocks + kCBlk - 1) / kCBlk;
-  a.n_items = n_bg * a.n_ig;
+  a.n_items = (n_bg + 3) / 4 * 4 * a.n_ig;   // block groups padded to whole lines
   if (a.n_items <= 0) return hipSuccess;
   a.per_xcd = (a.n_items + kNumXcd - 1) / kNumXcd;
   const int64_t grid = a.per_xcd * kNumXcd;

@@ -39,7 +39,7 @@ struct FArgs {
   float max_abs;
   int32_t vec_in;          // 1: n_in a multiple of, and volt aligned to, the inputs per workgroup
   int32_t vec_out;         // 1: t_offset % 8 == 0 and ring_stride % 8 == 0
-  int64_t n_items;         // block groups x input groups
+  int64_t n_items;         // block groups (padded to a multiple of 4) x input groups
   int64_t per_xcd;         // ceil(n_items / 8)
   const float* pfb;        // filterbank coefficients h[p*256 + n], p < TAPS (TAPS > 1 only)
 };
@@ -84,12 +84,17 @@ __global__ __launch_bounds__(256, (TAPS > 1 ? 2 : 3)) void fstage_kernel(FArgs a
   __shared__ float hs[TAPS > 1 ? TAPS * kFN : 1];                                // filterbank: 1 KB per tap
 
   const int tid = threadIdx.x;
-  // The n_ig workgroups of one block group read the same input rows; the
-  // XCD remap puts them on one XCD (one L2), one after another.
+  // Items run through 4 consecutive block groups of one input group (the
+  // four 32-byte pieces of each 128-byte ring line), then input groups, then
+  // the next 4 block groups.  The XCD remap keeps each run of items on one
+  // XCD (one L2): the n_ig workgroups of a block group read the same input
+  // rows, and the four pieces of a line merge there before going to HBM.
   const int64_t item = xcd_item(blockIdx.x, a.per_xcd);
   if ((int64_t)(blockIdx.x / kNumXcd) >= a.per_xcd || item >= a.n_items) return;
-  const int ig = (int)(item % a.n_ig);
-  const int64_t b0 = (item / a.n_ig) * kFBlk;
+  const int64_t rest = item >> 2;
+  const int ig = (int)(rest % a.n_ig);
+  const int64_t b0 = ((rest / a.n_ig) * 4 + (item & 3)) * kFBlk;
+  if (b0 >= a.n_blocks) return;
   const int i0 = ig * IN;
   const int f = tid >> 4;  // block of this FFT slot
   const int l = tid & 15;  // lane within the FFT
@@ -260,7 +265,7 @@ hipError_t launch_fstage(const FArgs& a, int taps, hipStream_t s) {
   FArgs b = a;
   b.n_ig = (a.n_in + in - 1) / in;
   b.vec_in = (a.n_in % in == 0) && ((reinterpret_cast<uintptr_t>(a.volt) & (in - 1)) == 0);
-  b.n_items = n_bg * b.n_ig;
+  b.n_items = (n_bg + 3) / 4 * 4 * b.n_ig;   // block groups padded to whole ring lines
   if (b.n_items <= 0) return hipSuccess;
   b.per_xcd = (b.n_items + kNumXcd - 1) / kNumXcd;
   const int64_t grid = b.per_xcd * kNumXcd;
