@@ -180,7 +180,10 @@ corr_status corr_channelise(corr_plan *plan, const void *d_volt, int64_t n_block
  * record counter: d_bad_records (optional device uint32, may be NULL) is
  * incremented once per record whose counter is not (first_counter + r) mod
  * 2^16 in at least one stream; the data are copied regardless.  No plan
- * needed; asynchronous on hip_stream (NULL = default stream).
+ * needed; asynchronous on hip_stream (NULL = default stream).  Any shape is
+ * accepted; the prototype's shape is fastest (words_per_record = 16,
+ * n_streams <= 4, n_records a multiple of 8, d_records and d_out 16-byte
+ * aligned).
  * CORR_E_INVAL for n_streams or words_per_record < 1, n_records < 0, or a
  * NULL buffer with n_records > 0; CORR_E_HIP if the launch fails. */
 corr_status corr_aggregate_w16(const uint16_t *d_records, int32_t n_streams, int32_t words_per_record,
