@@ -71,6 +71,30 @@ def test_aggregate_bit_exact_and_counters():
             assert np.array_equal(out.cpu().numpy().view(np.uint16), want)
 
 
+def test_aggregate_pointer_alignment():
+    """The same records at 2-, 4- and 16-byte aligned addresses (the generic
+    kernel, the per-record kernel with dword loads, and with 16-byte loads),
+    written to an output 16 bytes past an allocation boundary."""
+    ns, nr, wp, c0 = 4, 1024, 16, 300
+    rec, _ = synth.capture_records(seed=6, index=0, n_records=nr, n_streams=ns, w_per=wp, first_counter=c0)
+    rec[1, 500, 0] ^= 4                       # one record out of step in one stream
+    want, bad = oracle.aggregate_w16(rec, c0)
+    assert bad == 1
+    flat = torch.from_numpy(np.ascontiguousarray(rec).view(np.int16).reshape(-1)).to(DEV)
+    for off in (1, 2, 8):                     # int16 elements: 2, 4 and 16 bytes
+        say(f"[aggregate] record pointer offset {2 * off} bytes")
+        big = torch.zeros(flat.numel() + off, dtype=torch.int16, device=DEV)
+        big[off:] = flat
+        d = big[off:].view(ns, nr, wp + 1)
+        assert d.data_ptr() % 256 == 2 * off
+        out_big = torch.empty(nr * ns * wp + 8, dtype=torch.int16, device=DEV)
+        out = out_big[8:].view(nr, ns * wp)
+        o, b = aggregate_w16(d, first_counter=c0, out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(o.cpu().numpy().view(np.uint16), want)
+        assert int(b.cpu().item()) == 1
+
+
 @pytest.mark.parametrize("fmt", ["cw16", "cb8"])
 def test_complex_fstage_shapes(fmt):
     # 64 and 24: vector loads (8 inputs per workgroup); 13: bytewise loads
