@@ -13,7 +13,8 @@ HEADER = os.path.join(ROOT, "include", "corr.h")
 
 
 def _declared():
-    txt = open(HEADER).read()
+    with open(HEADER) as fh:
+        txt = fh.read()
     return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(corr_\w+)\s*\(", txt, flags=re.M)))
 
 
