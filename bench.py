@@ -65,15 +65,64 @@ def cpu_baseline(x_dev, n_channels: int) -> dict:
                            "sample": "1 channel x all 524800 products x 8000 samples on one thread"}}
 
 
+def cpu_other_configs() -> dict:
+    """The oracle on the other configurations, on the host's cores (all of
+    them, and one thread): C1 in full; one of C2's ten integrations (the
+    direct DFT F-stage on a fifth of its blocks -- one thread on a fortieth --
+    scaled, and
+    the X-engine on requantised samples of the same shape); C4's FP64
+    X-engine on 32 of its 1024 channels (one thread: 4 channels), scaled to
+    the whole configuration (channels are independent).  Seconds per
+    integration."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    threads = oracle.num_threads()
+
+    def timed(fn, one_thread=False):
+        if one_thread:
+            oracle.set_num_threads(1)
+        try:
+            t = time.perf_counter()
+            fn()
+            return time.perf_counter() - t
+        finally:
+            oracle.set_num_threads(threads)
+
+    res = {"host_threads": threads, "nproc": os.cpu_count(), "unit": "s per integration", "kind": "oracle"}
+    x1 = synth.ci8(1, 128, 64, 1000)
+    res["c1_x"] = {"all_cores": timed(lambda: oracle.xengine_ci8(x1)),
+                   "one_thread": timed(lambda: oracle.xengine_ci8(x1), True), "sample": "in full"}
+    v = synth.real_voltages(seed=2, index=0, n_blocks=2000, n_inputs=64)
+    f_all = timed(lambda: oracle.dft_real(v, 256)) * 5.0
+    f_one = timed(lambda: oracle.dft_real(v[: 250 * 256], 256), True) * 40.0
+    q = synth.ci8(2, 128, 64, 10000)
+    res["c2_f"] = {"all_cores": f_all, "one_thread": f_one,
+                   "sample": "2000 of 10000 blocks x 64 inputs, x5 (one thread: 250 blocks, x40)"}
+    res["c2_x"] = {"all_cores": timed(lambda: oracle.xengine_ci8(q)),
+                   "one_thread": timed(lambda: oracle.xengine_ci8(q), True),
+                   "sample": "128 channels x 64 inputs x 10000 samples, in full"}
+    x4 = np.stack([synth.complex_float(4, ch, 256, 4096) for ch in range(32)])
+    res["c4_x_fp64"] = {"all_cores": timed(lambda: oracle.xengine_cf64(x4)) * 1024 / 32,
+                        "one_thread": timed(lambda: oracle.xengine_cf64(x4[:4]), True) * 1024 / 4,
+                        "sample": "32 of 1024 channels (one thread: 4), scaled x32 (x256)"}
+    return res
+
+
 def serving(seconds: float, warm: float, rate: float, seed: int = 5) -> dict:
-    """Continuous-batching serving run.  Fifteen streams, one per (N_I, N_C)
-    in {16, 64, 128, 512, 1024} x {64, 256, 768}, each keep a device-resident
-    ring of 8000 complex int8 samples per channel and input (filled once by the
-    seeded generator, standing in for the instrument's ingest).  Integration
-    jobs arrive as a Poisson process (rate jobs/s); each picks a stream at
-    random and integrates its first T samples, T uniform in 1000..8000, into a
-    device result buffer.  Latency = result landed - scheduled arrival; jobs
-    arriving in the first `warm` seconds are excluded from the statistics."""
+    """Continuous-batching serving run (C5).  Fifteen streams, one per
+    (N_I, N_C) in {16, 64, 128, 512, 1024} x {64, 256, 768}, each keep a
+    device-resident ring of 8000 complex int8 samples per channel and input
+    (filled once by the seeded generator, standing in for the instrument's
+    ingest).  Integration jobs arrive as a Poisson process (rate jobs/s); each
+    picks a stream at random and integrates its first T samples, T uniform in
+    1000..8000, and its result goes to pinned host memory.  Two latencies per
+    job, both from its scheduled arrival: to the integration complete in
+    device memory, and to the result landed in host memory (the dump end
+    point).  Jobs arriving in the first `warm` seconds are excluded from the
+    statistics."""
     import numpy as np
     import torch
 
@@ -96,63 +145,90 @@ def serving(seconds: float, warm: float, rate: float, seed: int = 5) -> dict:
     t_rel = t_rel[t_rel < seconds]
     shapes = [(int(rng.choice(NIS)), int(rng.choice(NCS)), int(rng.integers(1000, TMAX + 1)))
               for _ in range(t_rel.size)]
-    max_res = 768 * 524800 * 8
-    n_slots = 16
-    slots = [torch.empty(max_res // 4, dtype=torch.int32, device="cuda:0") for _ in range(n_slots)]
-    free = list(range(n_slots))
+    # pinned host result buffers per (N_I, N_C): 2 for the arrays of 512 and
+    # 1024 inputs, 4 for the others; a job waits for a free one of its shape
+    bufs = {}
+    for n_in in NIS:
+        for n_ch in NCS:
+            P = n_in * (n_in + 1) // 2
+            bufs[(n_in, n_ch)] = [torch.empty((n_ch, P, 2), dtype=torch.int32, pin_memory=True)
+                                  for _ in range(2 if n_in >= 512 else 4)]
+    free = {k: list(range(len(v))) for k, v in bufs.items()}
     sched = Scheduler(16 << 30, n_streams=4)
 
     def submit(n_in, n_ch, T, slot, t_arr=None):
         ring = rings[(n_in, n_ch)]
-        return sched.submit(n_in, n_ch, T, slots[slot], d_samples=ring.data_ptr(), row_stride=TMAX,
+        return sched.submit(n_in, n_ch, T, bufs[(n_in, n_ch)][slot], d_samples=ring.data_ptr(), row_stride=TMAX,
                             t_arrival=t_arr)
 
     j0 = submit(16, 64, 1000, 0)
     while sched.poll(j0) is None:
         time.sleep(0.001)
-    inflight, done = {}, []
+    inflight, done, waiting = {}, [], []
     t0 = corr_sched_now() + 0.05
     k = 0
-    while k < len(shapes) or inflight:
+    last_log = time.time()
+    while k < len(shapes) or inflight or waiting:
         now = corr_sched_now()
         for jid in list(inflight):
             r = sched.poll(jid)
             if r is not None:
-                kk, slot = inflight.pop(jid)
+                kk, key, slot = inflight.pop(jid)
                 if r[0] != 0:
                     raise RuntimeError(f"serving job {kk} failed with status {r[0]}")
-                done.append((kk, t0 + t_rel[kk], r[2], r[3]))
-                free.append(slot)
-        while k < len(shapes) and t0 + t_rel[k] <= now and free:
-            slot = free.pop()
-            inflight[submit(*shapes[k], slot, t0 + t_rel[k])] = (k, slot)
+                done.append((kk, t0 + t_rel[kk], r[2], r[4], r[3]))
+                free[key].append(slot)
+        while k < len(shapes) and t0 + t_rel[k] <= now:
+            waiting.append(k)
             k += 1
+        for kk in list(waiting):
+            key = shapes[kk][:2]
+            if free[key]:
+                slot = free[key].pop()
+                inflight[submit(*shapes[kk], slot, t0 + t_rel[kk])] = (kk, key, slot)
+                waiting.remove(kk)
+        if time.time() - last_log > 10.0:
+            log(f"serving: {len(done)} of {len(shapes)} jobs done")
+            last_log = time.time()
         time.sleep(0.0002)
     stats = sched.stats()
     sched.close()
-    lat, wait, tint1, tint2, cm = [], [], [], [], 0
-    for kk, ta_sched, ta, td in sorted(done):
+    lat_d, lat_h, wait, tint1, tint2, cm = [], [], [], [], [], 0
+    for kk, ta_sched, ta, tv, td in sorted(done):
         if t_rel[kk] < warm:
             continue
         n_in, n_ch, T = shapes[kk]
-        lat.append(td - ta_sched)
+        lat_d.append(tv - ta_sched)
+        lat_h.append(td - ta_sched)
         wait.append(ta - ta_sched)
         tint1.append(T / 10e3)                 # 10 kHz channels (1.28 MHz / 128)
         tint2.append(T * n_ch / 1.28e6)        # the 1.28 MHz band split into N_C channels
         cm += n_ch * n_in * (n_in + 1) // 2 * T
-    lat = np.array(lat)
-    span = max(td for _, _, _, td in done) - (t0 + warm)
-    return {"jobs": int(lat.size), "offered_rate_per_s": rate, "seconds": seconds, "warmup_s": warm,
-            "throughput_jobs_per_s": lat.size / span, "throughput_tcmac_s": cm / span / 1e12,
-            "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
-                           "max": float(lat.max() * 1e3), "mean": float(lat.mean() * 1e3)},
+    lat_d, lat_h = np.array(lat_d), np.array(lat_h)
+    span = max(d[4] for d in done) - (t0 + warm)
+
+    def pct(a):
+        return {"p50": float(np.percentile(a, 50) * 1e3), "p99": float(np.percentile(a, 99) * 1e3),
+                "max": float(a.max() * 1e3), "mean": float(a.mean() * 1e3)}
+
+    def within(a):
+        return {"T_over_10kHz": float(np.mean(a < np.array(tint1))),
+                "T_times_NC_over_1.28MHz": float(np.mean(a < np.array(tint2)))}
+
+    big = np.array([shapes[kk][:2] == (1024, 768) for kk, *_ in sorted(done) if t_rel[kk] >= warm])
+    return {"jobs": int(lat_h.size), "offered_rate_per_s": rate, "seconds": seconds, "warmup_s": warm,
+            "throughput_jobs_per_s": lat_h.size / span, "throughput_tcmac_s": cm / span / 1e12,
+            "latency_ms": pct(lat_h), "latency_end": "result landed in the job's pinned host buffer",
+            "latency_device_ms": pct(lat_d),
+            "latency_device_end": "integration complete in device memory (completion word seen by the scheduler)",
+            "latency_ms_excl_1024x768": pct(lat_h[~big]) if (~big).any() else None,
             "admission_wait_ms_p99": float(np.percentile(wait, 99) * 1e3),
-            "frac_within_own_integration_time": {
-                "T_over_10kHz": float(np.mean(lat < np.array(tint1))),
-                "T_times_NC_over_1.28MHz": float(np.mean(lat < np.array(tint2)))},
-            "p99_below_50ms": bool(np.percentile(lat, 99) < 0.050),
-            "scheduler": stats, "streams": 4, "arena_GiB": 16, "rings_GB": 30.0,
-            "latency_end": "integration landed in the job's device result buffer"}
+            "frac_within_own_integration_time": within(lat_h),
+            "frac_within_own_integration_time_device": within(lat_d),
+            "p99_below_50ms": bool(np.percentile(lat_h, 99) < 0.050),
+            "p99_device_below_50ms": bool(np.percentile(lat_d, 99) < 0.050),
+            "scheduler": stats, "path": "device job queue, persistent int8 grids", "arena_GiB": 16,
+            "rings_GB": 30.0}
 
 
 # HBM bytes per launch of the C3 int8 kernel, from rocprofv3 FETCH_SIZE and
@@ -474,8 +550,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-ci4", action="store_true")
     ap.add_argument("--cpu-channels", type=int, default=64)
-    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-seconds", type=float, default=52.0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-other-configs", action="store_true")
     ap.add_argument("--mode", choices=["bench", "copy", "c2", "proto", "designs"], default="bench",
@@ -579,6 +656,37 @@ def main() -> int:
         fp32 = {"value": cmac / (fms / 1e3) / 1e12, "unit": "Tcmac/s", "ms": fms, "bitexact_vs_int8": same,
                 "peak_tcmac": perfmodel.fp32_cmac_peak() / 1e12,
                 "frac": cmac / (fms / 1e3) / perfmodel.fp32_cmac_peak()}
+    ci4 = None
+    if not args.no_ci4:
+        log("int8 engine on one byte per sample (CI4)")
+        b = (((x[..., 0] & 15) << 4) | (x[..., 1] & 15)).contiguous()     # the same samples, packed
+        g = Correlator(N_IN, N_CH, engine="i8", sample_type="ci4", max_abs=7, device="cuda:0")
+        g.correlate(b)
+        v4, _, _ = g.dump(1)
+        same4 = bool(torch.equal(v4, out_dev))
+        del v4
+        for _ in range(args.warmup):
+            g.correlate(b)
+            g.dump(0)
+        torch.cuda.synchronize()
+        evs4 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in range(args.steps)]
+        for k in range(args.steps):
+            evs4[k][0].record(stream)
+            g.correlate(b)
+            evs4[k][1].record(stream)
+            g.dump(0)
+        torch.cuda.synchronize()
+        ms4 = sorted(s_.elapsed_time(e_) for s_, e_ in evs4)
+        g.close()
+        del b
+        avg4 = sum(ms4) / len(ms4)
+        ci4 = {"value": cmac / (avg4 / 1e3) / 1e12, "unit": "Tcmac/s", "kernel_ms_avg": avg4,
+               "kernel_ms_median": ms4[len(ms4) // 2],
+               "frac_of_int8_peak": perfmodel.REAL_MACS_PER_CMAC * 2 * cmac / (avg4 / 1e3) / perfmodel.MI355X["int8_ops"],
+               "bitexact_vs_int8_pairs": same4, "input_bytes": N_CH * N_IN * N_T,
+               "note": "the C3 samples packed one byte per sample (re in the high nibble); beside, not replacing, "
+                       "the int8-pair headline"}
     del out_dev
 
     # roofline of the dominant kernel: int8 MFMA ops (4 real MACs = 8 ops per CMAC)
@@ -614,6 +722,8 @@ def main() -> int:
                                        stream=stream.cuda_stream)
             torch.cuda.synchronize()
         cpu = cpu_baseline(x, args.cpu_channels)
+        log("CPU oracle on C1, C2 and C4")
+        cpu["other_configs"] = cpu_other_configs()
         cpu["one_thread"]["gpu_int8_over_this"] = (cmac / (ms_per_step / 1e3) / 1e12) / cpu["one_thread"]["value"]
 
     value = cmac / (ms_per_step / 1e3) / 1e12
@@ -636,6 +746,7 @@ def main() -> int:
         "roofline": roof,
         "cpu_baseline": cpu,
         "fp32_plain": fp32,
+        "ci4": ci4,
         "serving": serve,
         "other_configs": others,
         "dump_ms": {"device": dump_dev_ms, "host_pinned": dump_host_ms, "bytes": N_CH * N_IN * (N_IN + 1) // 2 * 8},

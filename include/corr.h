@@ -21,7 +21,8 @@
  *                auto-correlation is written as exactly zero.
  *   Samples      complex, [n_channels][n_inputs][row_stride] with re, im
  *                interleaved; CORR_CI8 = int8 re, int8 im (2 B per sample),
- *                CORR_CF32 = float re, float im (8 B per sample).
+ *                CORR_CF32 = float re, float im (8 B per sample), CORR_CI4 =
+ *                one byte, re in the high nibble (1 B per sample).
  *   Memory       The caller owns every device buffer, including the workspace
  *                (size from corr_workspace_bytes); libcorr never allocates
  *                device memory.  The library owns only the host-side plan.
@@ -62,7 +63,14 @@ typedef enum {
 
 typedef enum {
     CORR_CF32 = 0,            /* complex float32 pairs                   */
-    CORR_CI8 = 1              /* complex int8 pairs                       */
+    CORR_CI8 = 1,             /* complex int8 pairs                       */
+    CORR_CI4 = 2              /* complex 4-bit, one byte per sample: re in
+                                 bits 7..4, im in bits 3..0, two's
+                                 complement (the "1-byte" mode of Sec. 5);
+                                 int8 engine, max_abs <= 7, X-engine input
+                                 only (fft_size 0); rows and the base
+                                 pointer 16-byte aligned, else
+                                 CORR_E_UNSUPPORTED                      */
 } corr_sample_t;
 
 typedef enum {
@@ -234,8 +242,9 @@ corr_status corr_seq_reset(corr_plan *plan);
  * accepted only with n_samples == 0 (an empty pass, nothing is done).
  * CORR_E_OVERFLOW (before any launch) if, for integer samples, the samples
  * accumulated since the last reset would exceed 2*max_abs^2*n <= 2^31-1 with
- * the int32 engine, or 2^24 with the FP32 engine on integer data (exact FP32
- * sums).  Asynchronous. */
+ * the int32 engine (2^31-1 over 256 for CORR_CI4, whose sums run at 256
+ * times V inside the engine), or 2^24 with the FP32 engine on integer data
+ * (exact FP32 sums).  Asynchronous. */
 corr_status corr_correlate(corr_plan *plan, const void *d_samples, int64_t n_samples,
                            int64_t row_stride);
 
@@ -254,8 +263,10 @@ corr_status corr_correlate(corr_plan *plan, const void *d_samples, int64_t n_sam
  * dividing by *n_samples_out is the caller's choice.  Synchronises the
  * plan's stream, so device faults surface here as CORR_E_HIP.
  * *n_samples_out: time samples accumulated in the integration (before reset).
- * *exact_out: 1 if every sum is provably exact (integer samples within the
- * bounds above), else 0.  Either out pointer may be NULL. */
+ * *exact_out: 1 if every sum copied to dst is provably exact, else 0: for
+ * INTEG, integer samples on the int8 or FP32 engine (within the bounds
+ * above); for LONGRUN, the same and 2 max_abs^2 n <= 2^53 over the n samples
+ * folded so far.  Either out pointer may be NULL. */
 corr_status corr_dump(corr_plan *plan, int32_t what, void *dst, int32_t dst_is_device,
                       int64_t *n_samples_out, int32_t *exact_out);
 
@@ -283,23 +294,35 @@ corr_status corr_dump_bytes(const corr_plan *plan, int32_t what, size_t *bytes);
  * Jobs from streams with different input and channel counts arrive at any
  * time (the real-time operation of Sec. 5; the batching of many cycles per
  * GPU call, Sec. 5).  corr_sched_submit never blocks: a job waits in a FIFO
- * queue until its HBM footprint (its samples, unless the caller supplies them
- * on the device, plus its plan workspace) fits in the caller's arena, then it
- * is admitted onto one of n_streams HIP streams, where it runs concurrently
- * with the other admitted jobs: samples are produced by the job's fill
- * callback (or read from the caller's buffer), correlated by the int8
- * X-engine (the job's plan), and the integration is copied to the job's
- * result buffer.  The job is complete when that copy has landed (the latency
- * end point); its arena region is then reused.  A job whose footprint exceeds the whole arena is refused at
- * submission (CORR_E_WORKSPACE).
+ * queue until its HBM footprint fits in the caller's arena (its samples when
+ * a fill callback produces them, its result when the destination is host
+ * memory) and one of 64 queue slots is free.  An admitted job is published
+ * on a job queue in the arena's head; persistent int8 X-engine grids (one for
+ * arrays of more than 64 inputs, one for the rest) take work items --
+ * (channel, baseline tile) pairs -- round robin from every published job, so
+ * jobs that arrive while others run are taken up by the grid already on the
+ * device, and their work overlaps.  No per-job plan is created and no kernel
+ * is launched per job; a new grid is launched only when work is published
+ * and none is running.  The job's device result is complete when its last
+ * item is done (the grid then writes a completion word in pinned host memory
+ * that the scheduler polls); a host destination then receives a copy, and
+ * the job is complete when that copy has landed (the latency end point).
+ * Samples whose rows are not 16-byte aligned (caller buffers with an odd row
+ * stride) are correlated through a per-job plan on one of n_streams streams
+ * instead.  A job whose footprint exceeds the whole arena is refused at
+ * submission (CORR_E_WORKSPACE).  The scheduler allocates, besides its host
+ * objects, 264 KB of pinned host memory (completion words and the staging of
+ * queue updates); no device memory.
  * ------------------------------------------------------------------------ */
 typedef struct corr_sched corr_sched;
 
-/* Writes the job's samples, complex int8 [n_channels][n_inputs][n_samples],
- * to device memory d_samples by queueing work on hip_stream; called from the
- * scheduler's thread when the job is admitted; must not block. */
+/* Writes the job's samples, complex int8 [n_channels][n_inputs][row_stride]
+ * (the first n_samples of each row; row_stride >= n_samples is chosen by the
+ * scheduler), to device memory d_samples by queueing work on hip_stream;
+ * called from the scheduler's thread when the job is admitted; must not
+ * block. */
 typedef void (*corr_fill_fn)(void *user, uint64_t job_id, void *d_samples, int64_t n_channels,
-                             int64_t n_inputs, int64_t n_samples, void *hip_stream);
+                             int64_t n_inputs, int64_t n_samples, int64_t row_stride, void *hip_stream);
 
 typedef struct {
     int32_t n_inputs;         /* N_I >= 1                                     */
@@ -325,9 +348,11 @@ typedef struct {
 /* Seconds on the clock the scheduler stamps completions with (monotonic). */
 double corr_sched_now(void);
 
-/* d_arena: caller-owned device memory (256-byte aligned) the scheduler carves
- * job footprints from; n_streams: concurrent jobs (1..16; streams of default
- * priority created and owned by the scheduler). */
+/* d_arena: caller-owned device memory (256-byte aligned) holding the job
+ * queue (its first 35 KB) and the job footprints; n_streams: streams for
+ * jobs on the per-job path (1..16).  All streams are of default priority,
+ * created and owned by the scheduler.  CORR_E_WORKSPACE if the arena is
+ * NULL, misaligned or smaller than the queue. */
 corr_status corr_sched_create(void *d_arena, size_t arena_bytes, int32_t n_streams, corr_sched **out);
 
 /* Queue a job.  t_arrival: its arrival time on corr_sched_now()'s clock (the
@@ -335,11 +360,13 @@ corr_status corr_sched_create(void *d_arena, size_t arena_bytes, int32_t n_strea
 corr_status corr_sched_submit(corr_sched *s, const corr_job_desc *job, double t_arrival, uint64_t *job_id);
 
 /* CORR_E_BUSY while job_id is queued or running.  Once it is complete:
- * CORR_OK (or the job's own error status), *n_samples_out, *t_admit and
- * *t_done (its admission and completion times) are written and the job
- * record is released; a second poll of the same id gives CORR_E_INVAL. */
+ * CORR_OK (or the job's own error status), *n_samples_out, *t_admit (its
+ * admission), *t_device (its integration complete in device memory, seen by
+ * the scheduler) and *t_done (its completion: the result in the job's
+ * destination) are written and the job record is released; a second poll of
+ * the same id gives CORR_E_INVAL.  Any out pointer may be NULL. */
 corr_status corr_sched_poll(corr_sched *s, uint64_t job_id, int64_t *n_samples_out, double *t_admit,
-                            double *t_done);
+                            double *t_device, double *t_done);
 
 /* stats[0..7] = submitted, admitted, completed, failed, queued now, running
  * now, peak arena bytes in use, arena bytes. */

@@ -8,7 +8,7 @@ runs in libcorr's kernels.
 from __future__ import annotations
 
 from . import _lib
-from ._lib import (CORR_CF32, CORR_CI8, CORR_DUMP_FOLD, CORR_DUMP_INTEG, CORR_DUMP_LONGRUN,
+from ._lib import (CORR_CF32, CORR_CI4, CORR_CI8, CORR_DUMP_FOLD, CORR_DUMP_INTEG, CORR_DUMP_LONGRUN,
                    CORR_DUMP_NO_RESET, CORR_X_F8, CORR_X_F16, CORR_X_FP32, CORR_X_I8, CorrError,
                    corr_aggregate_w16, corr_channelise, corr_cmac_design, corr_config, corr_correlate, corr_create, corr_destroy, corr_dump,
                    corr_dump_bytes, corr_job_desc, corr_ring_read, corr_sched_create, corr_sched_destroy,
@@ -25,7 +25,7 @@ __all__ = [
 ]
 
 ENGINES = {"fp32": CORR_X_FP32, "i8": CORR_X_I8, "f16": CORR_X_F16, "f8": CORR_X_F8}
-SAMPLE_TYPES = {"cf32": CORR_CF32, "ci8": CORR_CI8}
+SAMPLE_TYPES = {"cf32": CORR_CF32, "ci8": CORR_CI8, "ci4": CORR_CI4}
 # F-stage input formats: real int8; complex 5+5-bit in 16-bit words; complex 4+4-bit bytes
 VOLT_FORMATS = {"r8": 0, "cw16": 1, "cb8": 2}
 
@@ -120,42 +120,72 @@ class Correlator:
 
     # -- plan calls ---------------------------------------------------------
     def channelise(self, volt, first_seq: int, spectra_dbg=None) -> None:
+        """volt: device tensor [n_blocks*fft_size][n_inputs] (time-major) of the
+        plan's volt_format, plus pfb_taps - 1 blocks of history with a filterbank."""
         t = self._torch
         want = {"r8": (t.int8,), "cw16": (t.int16, t.uint16), "cb8": (t.uint8, t.int8)}[self.volt_format]
         assert volt.dtype in want and volt.is_contiguous() and volt.device == self.device
+        assert volt.dim() == 2 and volt.shape[1] == self.n_inputs, (tuple(volt.shape), self.n_inputs)
+        assert volt.shape[0] % self.cfg.fft_size == 0, "whole blocks only"
         # with a filterbank of P taps the input carries P - 1 blocks of history
         n_blocks = volt.shape[0] // self.cfg.fft_size - max(0, self.cfg.pfb_taps - 1)
+        assert n_blocks >= 0
         dbg = 0
         if spectra_dbg is not None:
             assert spectra_dbg.dtype == t.float32 and spectra_dbg.is_contiguous()
+            assert spectra_dbg.device == self.device
             assert spectra_dbg.numel() >= self.n_channels * self.n_inputs * n_blocks * 2
             dbg = spectra_dbg.data_ptr()
         corr_channelise(self.plan, volt.data_ptr(), n_blocks, first_seq, dbg)
 
     def correlate(self, samples=None, n_samples: int | None = None, row_stride: int = 0) -> None:
+        """samples: device tensor [n_channels][n_inputs][T][2] (int8 for ci8,
+        float32 for cf32) or [n_channels][n_inputs][T] (int8/uint8 bytes for
+        ci4); the first n_samples (default T) of each row are correlated.
+        None drains the F-stage ring."""
         if samples is None:
             corr_correlate(self.plan, 0, 0, 0)
             return
+        t = self._torch
+        if self.cfg.sample_type == CORR_CI4:
+            assert samples.dtype in (t.int8, t.uint8), samples.dtype
+            assert samples.dim() == 3, tuple(samples.shape)
+        else:
+            want = t.int8 if self.cfg.sample_type == CORR_CI8 else t.float32
+            assert samples.dtype == want, (samples.dtype, want)
+            assert samples.dim() == 4 and samples.shape[3] == 2, tuple(samples.shape)
         assert samples.device == self.device and samples.is_contiguous()
+        assert (samples.shape[0], samples.shape[1]) == (self.n_channels, self.n_inputs), tuple(samples.shape)
+        stride = samples.shape[2]
         if n_samples is None:
-            n_samples = samples.shape[2]
-        corr_correlate(self.plan, samples.data_ptr(), n_samples, row_stride)
+            n_samples = stride
+        assert 0 <= n_samples <= stride, (n_samples, stride)
+        assert row_stride in (0, stride), "a contiguous tensor's row stride is its time extent"
+        corr_correlate(self.plan, samples.data_ptr(), n_samples, stride)
 
     def correlate_ptr(self, d_samples: int, n_samples: int, row_stride: int = 0) -> None:
         """Raw form: device pointer to [n_channels][n_inputs][row_stride] samples."""
         corr_correlate(self.plan, d_samples, n_samples, row_stride)
 
+    def _dump_dtype(self, what: int):
+        t = self._torch
+        if what & CORR_DUMP_LONGRUN:
+            return t.float64
+        return t.int32 if self.engine == "i8" else t.float32
+
     def dump(self, what: int = CORR_DUMP_INTEG, out=None, device_out: bool = True):
         """Returns (tensor, n_samples, exact)."""
         t = self._torch
-        if what & CORR_DUMP_LONGRUN:
-            dtype = t.float64
-        else:
-            dtype = t.int32 if self.engine == "i8" else t.float32
-        if out is None and (what & (CORR_DUMP_INTEG | CORR_DUMP_LONGRUN)):
+        dtype = self._dump_dtype(what)
+        copies = bool(what & (CORR_DUMP_INTEG | CORR_DUMP_LONGRUN))
+        if out is None and copies:
             dev = self.device if device_out else t.device("cpu")
             out = t.empty((self.n_channels, self.n_products, 2), dtype=dtype, device=dev)
-        ptr = out.data_ptr() if out is not None else 0
+        elif out is not None and copies:
+            assert out.dtype == dtype and out.is_contiguous(), (out.dtype, dtype)
+            assert out.numel() >= self.n_channels * self.n_products * 2, out.numel()
+            assert out.device.type == "cpu" or out.device == self.device
+        ptr = out.data_ptr() if (out is not None and copies) else 0
         is_dev = out is not None and out.device.type == "cuda"
         n, exact = corr_dump(self.plan, what, ptr, is_dev)
         return out, n, exact
@@ -222,6 +252,11 @@ class Scheduler:
         j.fill_user = fill_user or None
         j.d_samples = d_samples or None
         j.row_stride = row_stride
+        import torch
+        P = n_inputs * (n_inputs + 1) // 2
+        assert dst.dtype == torch.int32 and dst.is_contiguous(), dst.dtype
+        assert dst.numel() >= n_channels * P * 2, (dst.numel(), n_channels * P * 2)
+        assert dst.device.type == "cpu" or dst.device == self.arena.device
         j.dst = dst.data_ptr()
         j.dst_is_device = int(dst.device.type == "cuda")
         return corr_sched_submit(self.handle, j, corr_sched_now() if t_arrival is None else t_arrival)

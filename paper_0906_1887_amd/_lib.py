@@ -21,6 +21,7 @@ CORR_E_UNSUPPORTED = -8
 
 CORR_CF32 = 0
 CORR_CI8 = 1
+CORR_CI4 = 2
 
 CORR_X_FP32 = 0
 CORR_X_I8 = 1
@@ -110,7 +111,7 @@ def lib():
         L.corr_sched_create.argtypes = [P, ctypes.c_size_t, I32, ctypes.POINTER(P)]
         L.corr_sched_submit.argtypes = [P, ctypes.POINTER(corr_job_desc), ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]
         L.corr_sched_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double),
-                                      ctypes.POINTER(ctypes.c_double)]
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.corr_sched_stats.argtypes = [P, ctypes.POINTER(I64)]
         L.corr_sched_destroy.argtypes = [P]
         for name in EXPORTED:
@@ -224,16 +225,19 @@ def corr_sched_submit(sched: int, job: corr_job_desc, t_arrival: float) -> int:
 
 
 def corr_sched_poll(sched: int, job_id: int):
-    """None while the job is queued or running; else (status, n_samples, t_admit, t_done)."""
+    """None while the job is queued or running; else (status, n_samples,
+    t_admit, t_done, t_device)."""
     n = ctypes.c_int64(0)
     ta = ctypes.c_double(0.0)
+    tv = ctypes.c_double(0.0)
     td = ctypes.c_double(0.0)
-    st = lib().corr_sched_poll(ctypes.c_void_p(sched), job_id, ctypes.byref(n), ctypes.byref(ta), ctypes.byref(td))
+    st = lib().corr_sched_poll(ctypes.c_void_p(sched), job_id, ctypes.byref(n), ctypes.byref(ta), ctypes.byref(tv),
+                               ctypes.byref(td))
     if st == CORR_E_BUSY:
         return None
     if st == CORR_E_INVAL:
         raise CorrError(st, "corr_sched_poll")
-    return int(st), int(n.value), float(ta.value), float(td.value)
+    return int(st), int(n.value), float(ta.value), float(td.value), float(tv.value)
 
 
 def corr_sched_stats(sched: int):

@@ -15,6 +15,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -41,6 +42,7 @@ struct Layout {
   size_t pfb = 0, pfb_bytes = 0;       // filterbank coefficients (pfb_taps > 1)
   size_t stage = 0, stage_bytes = 0;   // FP16/FP8 staged samples
   size_t mbits = 0, scales = 0;        // FP8 per-channel max and 1/s^2
+  size_t sync = 0, sync_bytes = 0;     // team-schedule sync words (128-row engine)
   int64_t stage_stride = 0;            // staged samples per row
   int stage_sb = 0;                    // staged bytes per complex sample
   size_t total = 0;
@@ -57,7 +59,12 @@ corr_status validate(const corr_config* c) {
   if (!c) return CORR_E_INVAL;
   if (c->n_inputs < 1 || c->n_inputs > 65536 || c->n_channels < 1) return CORR_E_INVAL;
   if (c->engine < CORR_X_FP32 || c->engine > CORR_X_F8) return CORR_E_INVAL;
-  if (c->sample_type != CORR_CF32 && c->sample_type != CORR_CI8) return CORR_E_INVAL;
+  if (c->sample_type != CORR_CF32 && c->sample_type != CORR_CI8 && c->sample_type != CORR_CI4) return CORR_E_INVAL;
+  if (c->sample_type == CORR_CI4) {
+    // nibble samples: int8 engine, |re|, |im| <= 7, X-engine input only
+    if (c->max_abs < 1 || c->max_abs > 7 || c->fft_size != 0) return CORR_E_INVAL;
+    if (c->engine != CORR_X_I8) return CORR_E_UNSUPPORTED;
+  }
   if (c->max_abs < 0 || c->max_abs > 127) return CORR_E_INVAL;
   if (c->engine == CORR_X_F16 || c->engine == CORR_X_F8) {
     // float samples staged to FP16 / FP8 in chunks of ring_samples
@@ -66,7 +73,7 @@ corr_status validate(const corr_config* c) {
     if (c->n_channels > 65535 || c->n_inputs > 65535) return CORR_E_UNSUPPORTED;
   }
   if (c->engine == CORR_X_I8) {
-    if (c->sample_type != CORR_CI8 && c->fft_size == 0) return CORR_E_INVAL;
+    if (c->sample_type == CORR_CF32 && c->fft_size == 0) return CORR_E_INVAL;
     if (c->max_abs < 1) return CORR_E_INVAL;  // int32 bound needs a declared range
   }
   if (c->pfb_taps < 0) return CORR_E_INVAL;
@@ -94,7 +101,7 @@ corr_status validate(const corr_config* c) {
 Layout layout_of(const corr_config* c) {
   Layout L;
   L.n_products = n_products(c->n_inputs);
-  L.bt = c->n_inputs > 64 ? 128 : 64;
+  L.bt = (c->n_inputs > 64 || c->sample_type == CORR_CI4) ? 128 : 64;   // CI4: 128-row tiles only
   const int64_t nb = (c->n_inputs + L.bt - 1) / L.bt;
   L.n_tiles = (int)(nb * (nb + 1) / 2);
   const int64_t tiles_total = (int64_t)c->n_channels * L.n_tiles;
@@ -136,6 +143,11 @@ Layout layout_of(const corr_config* c) {
     L.scales = off;
     off = align_up(off + (size_t)c->n_channels * 4, kAlign);
   }
+  if (L.bt == 128) {
+    L.sync = off;
+    L.sync_bytes = (size_t)corr::kNumXcd * corr::kTeamSyncStride * sizeof(uint32_t);
+    off = align_up(off + L.sync_bytes, kAlign);
+  }
   if (L.max_split > 1) {
     L.part = off;
     L.part_bytes = (size_t)L.max_split * L.acc_bytes;
@@ -155,6 +167,7 @@ struct corr_plan {
   std::vector<float2> tw_host;
   std::vector<float> pfb_host;   // filterbank coefficients (kept for the asynchronous upload)
   int64_t n_accum = 0;       // samples in the integration accumulator
+  int64_t n_long = 0;        // samples folded into the FP64 long-run accumulator
   bool acc_zero = true;      // accumulator logically zero (contents stale)
   bool error = false;
   bool seq_valid = false;
@@ -173,24 +186,126 @@ corr_status hip_fail(corr_plan* p, hipError_t e) {
 
 void* at(corr_plan* p, size_t off) { return p->ws + off; }
 
+// CUs of the current device and team-kernel workgroups per CU (cached per
+// device; 0 if unknown).
+struct TeamHw {
+  int cus = -1, per_cu = 0;
+};
+TeamHw team_hw() {
+  static TeamHw cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return TeamHw{0, 0};
+  TeamHw& h = cache[dev];
+  if (h.cus < 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+    h.per_cu = corr::team_blocks_per_cu();
+    h.cus = cus;
+  }
+  return h;
+}
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return (v && *v) ? std::atoi(v) : dflt;
+}
+
+// The team schedule (xeng_team_kernel) for 5 to 11 row panels of 128 inputs
+// when every XCD gets at least two steps per team: teams of n_full =
+// nb(nb-1)/2 workgroups in the slots the GPU holds at once.
+struct TeamShape {
+  int nb = 0, n_full = 0, teams = 0, grid = 0;
+};
+TeamShape team_shape(const corr_config& c) {
+  TeamShape t;
+  if (env_int("CORR_TEAM", 1) == 0) return t;
+  const TeamHw h = team_hw();
+  if (h.cus <= 0 || h.per_cu <= 0 || h.cus % corr::kNumXcd != 0) return t;
+  const int nb = (c.n_inputs + 127) / 128;
+  const int n_full = nb * (nb - 1) / 2;
+  const int slots = h.per_cu * h.cus / corr::kNumXcd;
+  if (nb < 5 || n_full > slots) return t;
+  const int teams = std::min(3, slots / n_full);
+  if ((int64_t)c.n_channels < 2LL * corr::kNumXcd * teams) return t;
+  t.nb = nb;
+  t.n_full = n_full;
+  t.teams = teams;
+  t.grid = slots * corr::kNumXcd;
+  return t;
+}
+hipError_t launch_team(const corr_config& c, const corr::XArgs& a, int elem, uint32_t* sync, size_t sync_bytes,
+                       hipStream_t st) {
+  const TeamShape ts = team_shape(c);
+  hipError_t e = corr::launch_fill_zero(sync, (int64_t)sync_bytes, st);
+  if (e != hipSuccess) return e;
+  corr::TeamArgs t;
+  std::memset(&t, 0, sizeof(t));
+  t.x = a;
+  t.sync = sync;
+  t.nb = ts.nb;
+  t.n_full = ts.n_full;
+  t.teams = ts.teams;
+  t.slack = env_int("CORR_TEAM_SLACK", 0);
+  t.spin_limit = env_int("CORR_TEAM_SPIN", 400);
+  return corr::launch_xeng_team(t, elem, ts.grid, st);
+}
+
 // Launch one X-engine pass over samples [n_ch][n_in][row_stride] (bytes per
 // sample `sb`), n_samples per row, into the plan's accumulator.
 corr_status xengine_pass(corr_plan* p, const void* x, int sb, int64_t n_samples, int64_t row_stride,
                          int elem = -1, const float* inv_scale2 = nullptr) {
-  const corr_config& c = p->cfg;
   const Layout& L = p->L;
-  if (n_samples == 0) return CORR_OK;
+  corr_xpass q;
+  std::memset(&q, 0, sizeof(q));
+  q.cfg = &p->cfg;
+  q.x = x;
+  q.sb = sb;
+  q.n_samples = n_samples;
+  q.row_stride = row_stride;
+  q.elem = elem;
+  q.inv_scale2 = inv_scale2;
+  q.acc = at(p, L.acc);
+  q.accumulate = p->acc_zero ? 0 : 1;
+  q.part = L.part_bytes ? at(p, L.part) : nullptr;
+  q.part_bytes = L.part_bytes;
+  q.sync = L.sync_bytes ? static_cast<uint32_t*>(at(p, L.sync)) : nullptr;
+  q.sync_bytes = L.sync_bytes;
+  q.stream = p->stream;
+  const corr_status st = corr_internal_xengine(&q);
+  if (st == CORR_E_HIP) p->error = true;
+  if (st == CORR_OK && n_samples > 0) p->acc_zero = false;
+  return st;
+}
+
+}  // namespace
+
+int corr_internal_split(const corr_config* c, int64_t n_samples) {
+  const Layout L = layout_of(c);
   const int64_t n_gran = (n_samples + kSplitGranule - 1) / kSplitGranule;
   // At least two granules (128 samples) per split: a 1000-sample integration
   // at N_I = 64 then takes 8 splits, 3 % faster than 4 splits of 256.
-  int split = std::min<int64_t>(L.max_split, std::max<int64_t>(1, n_gran / 2));
+  int split = (int)std::min<int64_t>(L.max_split, std::max<int64_t>(1, n_gran / 2));
   const int64_t gran_per_split = (n_gran + split - 1) / split;
-  split = (int)((n_gran + gran_per_split - 1) / gran_per_split);
+  return (int)((n_gran + gran_per_split - 1) / gran_per_split);
+}
+
+size_t corr_internal_sync_bytes() { return (size_t)corr::kNumXcd * corr::kTeamSyncStride * sizeof(uint32_t); }
+
+corr_status corr_internal_xengine(const corr_xpass* q) {
+  const corr_config& c = *q->cfg;
+  const Layout L = layout_of(&c);
+  const int64_t n_samples = q->n_samples;
+  const int sb = q->sb;
+  if (n_samples == 0) return CORR_OK;
+  const int64_t n_gran = (n_samples + kSplitGranule - 1) / kSplitGranule;
+  const int split = corr_internal_split(&c, n_samples);
+  const int64_t gran_per_split = (n_gran + split - 1) / split;
+  if (split > 1 && (!q->part || q->part_bytes < (size_t)split * L.acc_bytes)) return CORR_E_WORKSPACE;
 
   corr::XArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.x = x;
-  a.row_stride_b = row_stride * sb;
+  a.x = q->x;
+  a.row_stride_b = q->row_stride * sb;
   a.ch_stride_b = (int64_t)c.n_inputs * a.row_stride_b;
   a.k_bytes = n_samples * sb;
   a.k_split_bytes = gran_per_split * kSplitGranule * sb;
@@ -204,30 +319,37 @@ corr_status xengine_pass(corr_plan* p, const void* x, int sb, int64_t n_samples,
   a.n_items = (int32_t)items;
   a.per_xcd = (int32_t)((items + corr::kNumXcd - 1) / corr::kNumXcd);
   const bool direct = (split == 1);
-  a.out = direct ? at(p, L.acc) : at(p, L.part);
+  a.out = direct ? q->acc : q->part;
   a.out_split_stride = direct ? 0 : (int64_t)c.n_channels * L.n_products;
-  a.accumulate = direct ? (p->acc_zero ? 0 : 1) : 0;
-  a.inv_scale2 = inv_scale2;
-  const bool aligned = (a.row_stride_b % 16 == 0) && ((reinterpret_cast<uintptr_t>(x) & 15) == 0);
+  a.accumulate = direct ? q->accumulate : 0;
+  a.inv_scale2 = q->inv_scale2;
+  const bool aligned = (a.row_stride_b % 16 == 0) && ((reinterpret_cast<uintptr_t>(q->x) & 15) == 0);
+  const bool ci4 = q->elem == corr::kElemCI4;
+  if (ci4 && !aligned) return CORR_E_UNSUPPORTED;   // nibble rows must be 16-byte aligned
+  const bool team = c.engine == CORR_X_I8 && (q->elem < 0 || ci4) && aligned && direct && L.bt == 128 && q->sync &&
+                    q->sync_bytes >= corr_internal_sync_bytes() && team_shape(c).grid > 0;
 
   hipError_t e;
   const bool is_int = (c.engine == CORR_X_I8);
-  if (elem >= 0)
-    e = corr::launch_xeng_mfma(a, elem, L.bt, p->stream);  // staged FP16 / FP8 rows are aligned
+  if (team)
+    e = launch_team(c, a, ci4 ? corr::kElemCI4 : corr::kElemI8, q->sync, q->sync_bytes, q->stream);
+  else if (q->elem >= 0)
+    e = corr::launch_xeng_mfma(a, q->elem, L.bt, q->stream);  // staged FP16 / FP8 rows and CI4 rows are aligned
   else if (c.engine == CORR_X_I8)
-    e = aligned ? corr::launch_xeng_mfma(a, corr::kElemI8, L.bt, p->stream)
-                : corr::launch_xeng_i8(a, L.bt, false, p->stream);
+    e = aligned ? corr::launch_xeng_mfma(a, corr::kElemI8, L.bt, q->stream)
+                : corr::launch_xeng_i8(a, L.bt, false, q->stream);
   else
-    e = corr::launch_xeng_f32(a, sb, L.bt, aligned, p->stream);
-  if (e != hipSuccess) return hip_fail(p, e);
+    e = corr::launch_xeng_f32(a, sb, L.bt, aligned, q->stream);
+  if (e != hipSuccess) return CORR_E_HIP;
   if (!direct) {
-    e = corr::launch_reduce_splits(at(p, L.part), (int64_t)c.n_channels * L.n_products, split, at(p, L.acc),
-                                   p->acc_zero ? 0 : 1, is_int, p->stream);
-    if (e != hipSuccess) return hip_fail(p, e);
+    e = corr::launch_reduce_splits(q->part, (int64_t)c.n_channels * L.n_products, split, q->acc, q->accumulate,
+                                   is_int, q->stream);
+    if (e != hipSuccess) return CORR_E_HIP;
   }
-  p->acc_zero = false;
   return CORR_OK;
 }
+
+namespace {
 
 // Integer-sample bounds: |Re V|, |Im V| <= 2 max_abs^2 n.
 bool within(const corr_config& c, int64_t n, double limit) {
@@ -408,15 +530,20 @@ corr_status corr_correlate(corr_plan* p, const void* d_samples, int64_t n_sample
     } else {
       if (n_samples < 0 || row_stride < 0) return CORR_E_INVAL;
       x = d_samples;
-      sb = (c.sample_type == CORR_CI8) ? 2 : 8;
+      sb = (c.sample_type == CORR_CI8) ? 2 : (c.sample_type == CORR_CI4 ? 1 : 8);
       n = n_samples;
       stride = row_stride == 0 ? n_samples : row_stride;
       if (stride < n) return CORR_E_INVAL;
-      if ((reinterpret_cast<uintptr_t>(x) % (sb == 8 ? 4 : 2)) != 0) return CORR_E_INVAL;
+      if ((reinterpret_cast<uintptr_t>(x) % (sb == 8 ? 4 : sb)) != 0) return CORR_E_INVAL;
+      // CI4 rows are staged 16 bytes at a time
+      if (c.sample_type == CORR_CI4 && n > 0 && ((reinterpret_cast<uintptr_t>(x) % 16) != 0 || stride % 16 != 0))
+        return CORR_E_UNSUPPORTED;
     }
     const int64_t total = p->n_accum + n;
     if (c.max_abs > 0) {
-      if (c.engine == CORR_X_I8 && !within(c, total, 2147483647.0)) return CORR_E_OVERFLOW;
+      // CI4 sums run at 256 times the visibility inside the engine
+      const double i32 = c.sample_type == CORR_CI4 ? 2147483647.0 / 256.0 : 2147483647.0;
+      if (c.engine == CORR_X_I8 && !within(c, total, i32)) return CORR_E_OVERFLOW;
       if (c.engine == CORR_X_FP32 && !within(c, total, 16777216.0)) return CORR_E_OVERFLOW;
     }
     if (c.engine == CORR_X_F16 || c.engine == CORR_X_F8) {
@@ -445,7 +572,7 @@ corr_status corr_correlate(corr_plan* p, const void* d_samples, int64_t n_sample
       p->n_accum = total;
       return CORR_OK;
     }
-    const corr_status s = xengine_pass(p, x, sb, n, stride);
+    const corr_status s = xengine_pass(p, x, sb, n, stride, c.sample_type == CORR_CI4 && d_samples ? corr::kElemCI4 : -1);
     if (s != CORR_OK) return s;
     p->n_accum = total;
     if (d_samples == nullptr) p->ring_fill = 0;
@@ -558,6 +685,7 @@ corr_status corr_dump(corr_plan* p, int32_t what, void* dst, int32_t dst_is_devi
       e = corr::launch_fold_f64(static_cast<double*>(at(p, L.longrun)), at(p, L.acc),
                                 (int64_t)c.n_channels * L.n_products * 2, is_int, p->stream);
       if (e != hipSuccess) return hip_fail(p, e);
+      p->n_long += p->n_accum;
     }
     const hipMemcpyKind kind = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (integ) {
@@ -581,8 +709,12 @@ corr_status corr_dump(corr_plan* p, int32_t what, void* dst, int32_t dst_is_devi
     if (integ && p->acc_zero && !dst_is_device) std::memset(dst, 0, L.acc_bytes);
     if (n_samples_out) *n_samples_out = p->n_accum;
     if (exact_out) {
+      // Integer samples on the exact engines: every integration is exact
+      // (corr_correlate refuses anything past the bound); the FP64 long-run
+      // sum of exact integers stays exact while 2 max_abs^2 n_long <= 2^53.
       const bool exact_engine = (c.engine == CORR_X_I8 || c.engine == CORR_X_FP32) && c.max_abs > 0;
-      *exact_out = (integ && exact_engine) || (longrun && exact_engine) ? 1 : 0;
+      const bool long_exact = exact_engine && within(c, p->n_long, 9007199254740992.0);
+      *exact_out = (integ && exact_engine) || (longrun && long_exact) ? 1 : 0;
     }
     if (!(what & CORR_DUMP_NO_RESET)) {
       p->acc_zero = true;

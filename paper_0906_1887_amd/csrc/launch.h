@@ -11,8 +11,17 @@ struct FArgs;
 
 // int8 MFMA X-engine; bt = 64 or 128; aligned: rows and base 16-byte aligned.
 hipError_t launch_xeng_i8(const XArgs& a, int bt, bool aligned, hipStream_t s);
-// Matrix-core X-engine for 16-byte aligned rows; elem = kElemI8 / kElemF16 / kElemF8.
+// Matrix-core X-engine for 16-byte aligned rows; elem = kElemI8 / kElemF16 / kElemF8
+// (bt 64 or 128), or kElemCI4 (bt 128).
 hipError_t launch_xeng_mfma(const XArgs& a, int elem, int bt, hipStream_t s);
+// Team-scheduled 128-row int8 engine (persistent grid of `grid` workgroups).
+hipError_t launch_xeng_team(const TeamArgs& t, int elem, int grid, hipStream_t s);
+// Workgroups of the team kernel one CU holds at once (0 if unknown).
+int team_blocks_per_cu();
+// Serving grid over the device job queue (int8, aligned rows).
+// Tiles of bt = 64 or 128 rows: a grid serves only the jobs of its tile size.
+hipError_t launch_xeng_serve(const ServeQueue& q, int bt, int grid, hipStream_t s);
+int serve_blocks_per_cu(int bt);
 // FP32 X-engine; sample_bytes = 8 (complex float32) or 2 (complex int8).
 hipError_t launch_xeng_f32(const XArgs& a, int sample_bytes, int bt, bool aligned, hipStream_t s);
 hipError_t launch_reduce_splits(const void* part, int64_t n_pairs, int n_split, void* acc, int accumulate,

@@ -605,6 +605,30 @@ __device__ __forceinline__ void mfma_tile_128(const XArgs& a, int8_t* lds, int c
     }
 }
 
+// CI4 samples (one byte per complex sample: re in bits 7..4, im in bits 3..0,
+// two's complement nibbles, the "1-byte" mode of Sec. 5) are unpacked in
+// registers into int8 operands scaled by 16: the byte's high nibble with the
+// low nibble cleared is 16 re, and the low nibble shifted up is 16 im, both
+// exact in int8 for |re|, |im| <= 7.  Operand bytes run [16 re of 4 samples,
+// 16 im of the same 4, 16 re of the next 4, 16 im of those]; the same order
+// in A and B makes A B^T = sum (re re' + im im') = Re V (times 256).
+constexpr uint32_t kHiNib = 0xF0F0F0F0u;
+__device__ __forceinline__ v4i ci4_plain(int w0, int w1) {
+  const uint32_t u0 = (uint32_t)w0, u1 = (uint32_t)w1;
+  return v4i{(int)(u0 & kHiNib), (int)((u0 << 4) & kHiNib), (int)(u1 & kHiNib), (int)((u1 << 4) & kHiNib)};
+}
+// -16 re per byte of a high-nibble word: flip the nibble and add 1 in it; a
+// carry out of a byte (re = 0) lands in the next byte's clear low nibble and
+// is masked off.
+__device__ __forceinline__ uint32_t neg_hi_nibbles(uint32_t x) { return ((x ^ kHiNib) + 0x10101010u) & kHiNib; }
+// Operands of -iA = (im, -re) in the same byte order: A' B^T = sum (im re' -
+// re im') = Im V (times 256).
+__device__ __forceinline__ v4i ci4_rotm(int w0, int w1) {
+  const uint32_t u0 = (uint32_t)w0, u1 = (uint32_t)w1;
+  return v4i{(int)((u0 << 4) & kHiNib), (int)neg_hi_nibbles(u0 & kHiNib), (int)((u1 << 4) & kHiNib),
+             (int)neg_hi_nibbles(u1 & kHiNib)};
+}
+
 // int8 variant of mfma_tile_128 on v_mfma_i32_16x16x64_i8: the same staging,
 // pipeline and 64 x 64 wave tile, as 4 x 4 blocks of 16 x 16.  Each fragment
 // read is one contiguous 1 KB of LDS (16 rows x 64 bytes), and the MFMA moves
@@ -619,7 +643,7 @@ __device__ __forceinline__ void mfma_tile_128_i8(const XArgs& a, int8_t* lds, in
   constexpr int STAGE = PANEL * (DIAG ? 1 : 2);
   constexpr int QPW = BT / 16 / 4;           // 1 KB load instructions per operand per wave
   constexpr int LPW = QPW * (DIAG ? 1 : 2);  // load instructions per wave per stage
-  static_assert(EK == kElemI8, "16 x 16 x 64 tile is the int8 engine");
+  static_assert(EK == kElemI8 || EK == kElemCI4, "16 x 16 x 64 tile is the int8 engine");
 
   const int8_t* __restrict__ xc = static_cast<const int8_t*>(a.x) + (int64_t)ch * a.ch_stride_b;
   const int64_t k0 = (int64_t)split * a.k_split_bytes;
@@ -748,19 +772,21 @@ __device__ __forceinline__ void mfma_tile_128_i8(const XArgs& a, int8_t* lds, in
   };
   auto compute = [&](auto sk, const v4i (&af)[4], const v4i (&bf)[4]) {
     constexpr bool SK = decltype(sk)::value;
+    if constexpr (EK != kElemCI4) {   // CI4 stages run through compute_ci4
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int n = 0; n < 4; ++n)
-        if (!(SK && n > m)) vr[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[m], bf[n], vr[m][n], 0, 0, 0);
-    v4i ra[4];
+        for (int n = 0; n < 4; ++n)
+          if (!(SK && n > m)) vr[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[m], bf[n], vr[m][n], 0, 0, 0);
+      v4i ra[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) ra[m] = rotm4<kElemI8>(af[m]);
+      for (int m = 0; m < 4; ++m) ra[m] = rotm4<kElemI8>(af[m]);
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int n = 0; n < 4; ++n)
-        if (!(SK && n > m)) vi[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ra[m], bf[n], vi[m][n], 0, 0, 0);
+        for (int n = 0; n < 4; ++n)
+          if (!(SK && n > m)) vi[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ra[m], bf[n], vi[m][n], 0, 0, 0);
+    }
   };
 
   if (n_st > 0) {
@@ -776,6 +802,57 @@ __device__ __forceinline__ void mfma_tile_128_i8(const XArgs& a, int8_t* lds, in
     }
     return;
   }
+  // CI4: a stage's 16 packed samples per lane feed two K steps (dwords 0-1
+  // of every A and B fragment the first, 2-3 the second).  Each step's
+  // operands are unpacked just before its 32 MFMAs; once the second step's
+  // are unpacked the packed registers take the next stage's LDS reads, which
+  // then run under the second step's MFMAs.
+  auto unpack_ci4 = [&](int h, const v4i (&pa)[4], const v4i (&pb)[4], v4i (&ua)[4], v4i (&ub)[4]) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      ua[m] = ci4_plain(pa[m][2 * h], pa[m][2 * h + 1]);
+      ub[m] = ci4_plain(pb[m][2 * h], pb[m][2 * h + 1]);
+    }
+  };
+  auto compute_ci4 = [&](auto sk, const v4i (&ua)[4], const v4i (&ub)[4]) {
+    constexpr bool SK = decltype(sk)::value;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+        if (!(SK && n > m)) vr[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ua[m], ub[n], vr[m][n], 0, 0, 0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      // -iA = (im, -re): the operand's im words, and its re words negated
+      const v4i a = ua[m];
+      const v4i ra = {a[1], (int)neg_hi_nibbles((uint32_t)a[0]), a[3], (int)neg_hi_nibbles((uint32_t)a[2])};
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+        if (!(SK && n > m)) vi[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ra, ub[n], vi[m][n], 0, 0, 0);
+    }
+  };
+  auto run_ci4 = [&](auto sk) {
+    constexpr int NM = (DIAG && decltype(sk)::value) ? 20 : 32;   // MFMAs per K step
+    v4i pa[4], pb[4], ua[4], ub[4];
+    if (n_st > 0) read(0, pa, pb);
+    for (int s = 0; s < n_st; ++s) {
+      unpack_ci4(0, pa, pb, ua, ub);
+      compute_ci4(sk, ua, ub);
+      unpack_ci4(1, pa, pb, ua, ub);
+      if (s + 1 < n_st) {
+        arrive(s + 1);
+        if (s + kMNS < n_st) issue(s + kMNS);
+        read(s + 1, pa, pb);
+      }
+      compute_ci4(sk, ua, ub);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, NM - 8, 0);
+    }
+  };
   auto run = [&](auto sk) {
     constexpr int NM = (DIAG && decltype(sk)::value) ? 20 : 32;   // MFMAs per stage
     v4i af0[4], bf0[4], af1[4], bf1[4];
@@ -799,8 +876,13 @@ __device__ __forceinline__ void mfma_tile_128_i8(const XArgs& a, int8_t* lds, in
     }
     if (n_st > 0) compute(sk, af0, bf0);
   };
-  if (DIAG && wm == wn) run(std::true_type{});
-  else run(std::false_type{});
+  if constexpr (EK == kElemCI4) {
+    if (DIAG && wm == wn) run_ci4(std::true_type{});
+    else run_ci4(std::false_type{});
+  } else {
+    if (DIAG && wm == wn) run(std::true_type{});
+    else run(std::false_type{});
+  }
 
   // Epilogue.  32 x 32 accumulator layout: register r of lane l holds row
   // 8*(r/4) + 4*(l/32) + r%4, column l%32.
@@ -817,8 +899,9 @@ __device__ __forceinline__ void mfma_tile_128_i8(const XArgs& a, int8_t* lds, in
         if (i < a.n_in && j <= i) {
           const int64_t off = (int64_t)split * a.out_split_stride + (int64_t)ch * a.n_products + tri_index(i, j);
           int2* pp = static_cast<int2*>(a.out) + off;
-          const int re = vr[m][n][r];
-          const int im = (i == j) ? 0 : vi[m][n][r];
+          // CI4 operands are 16 x the sample parts: the sums are 256 V exactly
+          const int re = EK == kElemCI4 ? (vr[m][n][r] >> 8) : vr[m][n][r];
+          const int im = (i == j) ? 0 : (EK == kElemCI4 ? (vi[m][n][r] >> 8) : vi[m][n][r]);
           if (a.accumulate) {
             int2 o = *pp;
             o.x += re;
@@ -844,13 +927,96 @@ __global__ __launch_bounds__(256, 2) void xeng_mfma_128_kernel(XArgs a) {
   const int ch = (int)(rest / a.n_split);
   int I, J;
   tile_decode(tile, I, J);
-  if constexpr (EK == kElemI8) {
+  if constexpr (EK == kElemI8 || EK == kElemCI4) {
     if (I == J) mfma_tile_128_i8<EK, true>(a, lds, ch, split, I, J);
     else mfma_tile_128_i8<EK, false>(a, lds, ch, split, I, J);
   } else {
     if (I == J) mfma_tile_128<EK, true>(a, lds, ch, split, I, J);
     else mfma_tile_128<EK, false>(a, lds, ch, split, I, J);
   }
+}
+
+// Team schedule of the 128-row int8 engine for arrays of 5 to 11 row panels
+// (N_I from 513 to 1408).  A persistent grid of exactly the workgroups the GPU
+// holds at once; the slots of each XCD form teams of n_full workgroups, one
+// per off-diagonal tile of a channel, and a team works through the XCD's
+// channels one step (channel) at a time.  Every member of a team runs the same
+// amount of work (a full 128 x 128 tile over all samples) and starts a step
+// when the whole team has finished the step before (give or take `slack`
+// steps), so the eight or so tiles that read each 64-byte piece of a row panel
+// fetch it within a short window and the XCD's L2 serves all but the first.
+// Diagonal tiles (half the loads, 9/16 of the matrix work) would break that
+// rhythm; they form a per-XCD queue drained by the spare slots and, at the
+// end, by the team members.  The waits are bounded (spin_limit polls): they
+// only shape the timing and never decide a result, so a member that gives up
+// waiting still computes its tile exactly.
+template <int EK>
+__global__ __launch_bounds__(256, 2) void xeng_team_kernel(TeamArgs t) {
+  __shared__ __attribute__((aligned(1024))) int8_t lds[kMNS * 2 * 128 * kMKC];
+  __shared__ int next_item;
+  const XArgs& a = t.x;
+  const int xcd = (int)(blockIdx.x % kNumXcd);
+  const int slot = (int)(blockIdx.x / kNumXcd);
+  const int c0 = (int)(((int64_t)xcd * a.n_ch) / kNumXcd);
+  const int c1 = (int)(((int64_t)(xcd + 1) * a.n_ch) / kNumXcd);
+  uint32_t* sync = t.sync + xcd * kTeamSyncStride;
+  if (slot < t.teams * t.n_full) {
+    const int team = slot / t.n_full;
+    const int member = slot % t.n_full;
+    int I, J;
+    tile_decode(member, I, J);      // strictly lower tile m = I(I-1)/2 + J
+    I += 1;
+    uint32_t* ctr = sync + kTeamSyncLine * team;
+    for (int k = 0;; ++k) {
+      const int ch = c0 + k * t.teams + team;
+      if (ch >= c1) break;
+      if (threadIdx.x == 0 && k > t.slack) {
+        const uint32_t target = (uint32_t)(t.n_full * (k - t.slack));
+        for (int w = 0; w < t.spin_limit; ++w) {
+          if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+          __builtin_amdgcn_s_sleep(4);
+        }
+      }
+      __syncthreads();              // also: the previous tile's LDS reads are done
+      mfma_tile_128_i8<EK, false>(a, lds, ch, 0, I, J);
+      if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  // Diagonal tiles of this XCD's channels, channel-major.
+  const int n_diag = (c1 - c0) * t.nb;
+  uint32_t* q = sync + kTeamSyncLine * t.teams;
+  for (;;) {
+    __syncthreads();                // previous tile's LDS reads done; next_item free
+    if (threadIdx.x == 0)
+      next_item = (int)__hip_atomic_fetch_add(q, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int idx = next_item;
+    if (idx >= n_diag) break;
+    const int ch = c0 + idx / t.nb;
+    const int I = idx % t.nb;
+    mfma_tile_128_i8<EK, true>(a, lds, ch, 0, I, I);
+  }
+}
+
+hipError_t launch_xeng_team(const TeamArgs& t, int elem, int grid, hipStream_t s) {
+  if (elem == kElemCI4) hipLaunchKernelGGL(xeng_team_kernel<kElemCI4>, dim3((unsigned)grid), dim3(256), 0, s, t);
+  else hipLaunchKernelGGL(xeng_team_kernel<kElemI8>, dim3((unsigned)grid), dim3(256), 0, s, t);
+  return hipGetLastError();
+}
+
+int team_blocks_per_cu() {
+  int n = 0, m = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, xeng_team_kernel<kElemI8>, 256, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, xeng_team_kernel<kElemCI4>, 256, 0) != hipSuccess) return 0;
+  return n < m ? n : m;
+}
+
+// Diagonal or off-diagonal tile of the BT-row engine (one instantiation site
+// for every kernel that runs BT-row tiles).
+template <int EK, int BT>
+__device__ __forceinline__ void mfma_tile_any(const XArgs& a, int8_t* lds, int ch, int split, int I, int J) {
+  if (I == J) mfma_tile<EK, BT, true>(a, lds, ch, split, I, J);
+  else mfma_tile<EK, BT, false>(a, lds, ch, split, I, J);
 }
 
 template <int EK, int BT>
@@ -865,8 +1031,91 @@ __global__ __launch_bounds__(256, 2) void xeng_mfma_kernel(XArgs a) {
   const int ch = (int)(rest / a.n_split);
   int I, J;
   tile_decode(tile, I, J);
-  if (I == J) mfma_tile<EK, BT, true>(a, lds, ch, split, I, J);
-  else mfma_tile<EK, BT, false>(a, lds, ch, split, I, J);
+  mfma_tile_any<EK, BT>(a, lds, ch, split, I, J);
+}
+
+// Serving: a device queue of integration jobs shared by persistent grids.
+// The host scheduler publishes each admitted job in a slot (its sample and
+// output pointers and shape) and lists the active slots; every workgroup of
+// every running serving grid claims work items -- (channel, tile) pairs of
+// some job -- from the listed jobs in turn (round robin over the jobs, so a
+// small job is not queued behind a large one), runs the tile over all of the
+// job's samples, and counts it done.  The workgroup that finishes a job's
+// last item writes the job's completion word in host memory.  A workgroup
+// that finds no work for idle_polls polls exits, so a grid ends soon after
+// the queue drains.
+__device__ __forceinline__ uint64_t sys_load64(const void* p) {
+  return __hip_atomic_load(static_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+template <int BT>
+__global__ __launch_bounds__(256, 2) void xeng_serve_kernel(ServeQueue q) {
+  __shared__ __attribute__((aligned(1024))) int8_t lds[kMNS * 2 * BT * kMKC];
+  __shared__ ServeJob job;
+  __shared__ int s_slot, s_item;
+  for (;;) {
+    __syncthreads();   // the previous tile's LDS reads and `job` uses are done
+    if (threadIdx.x == 0) {
+      int slot = -1;
+      uint64_t claimed = 0;
+      for (int idle = 0; slot < 0 && idle < q.idle_polls; ++idle) {
+        const int n = __hip_atomic_load(q.active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (n > 0 && n <= q.n_slots) {
+          const uint32_t r = __hip_atomic_fetch_add(q.rr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          for (int a = 0; a < n && slot < 0; ++a) {
+            const int e = __hip_atomic_load(q.active + 1 + (int)((r + (uint32_t)a) % (uint32_t)n), __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_SYSTEM);
+            if (((e & kServeSmall) != 0) != (BT == 64)) continue;   // the other tile size's job
+            const int s = e & (kServeSmall - 1);
+            if (s >= q.n_slots) continue;
+            uint64_t* cw = q.claim + (size_t)s * (kServeLine / 2);
+            const uint64_t lim = sys_load64(q.limit + (size_t)s * (kServeLine / 2));
+            uint64_t w = __hip_atomic_load(cw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            while (w < lim) {
+              if (__hip_atomic_compare_exchange_strong(cw, &w, w + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT)) {
+                slot = s;
+                claimed = w;
+                break;
+              }
+            }
+          }
+        }
+        if (slot < 0) __builtin_amdgcn_s_sleep(8);
+      }
+      if (slot >= 0) {
+        const uint64_t* src = reinterpret_cast<const uint64_t*>(q.slots + slot);
+        uint64_t* dst = reinterpret_cast<uint64_t*>(&job);
+        for (int k = 0; k < (int)(sizeof(ServeJob) / 8); ++k) dst[k] = sys_load64(src + k);
+      }
+      s_slot = slot;
+      s_item = slot >= 0 ? (int)(claimed - job.base) : 0;
+    }
+    __syncthreads();
+    const int slot = s_slot;
+    if (slot < 0) return;
+    const XArgs a = job.x;
+    const int tile = s_item % a.n_tiles;
+    const int ch = s_item / a.n_tiles;
+    int I, J;
+    tile_decode(tile, I, J);
+    if constexpr (BT == 128) {
+      if (I == J) mfma_tile_128_i8<kElemI8, true>(a, lds, ch, 0, I, J);
+      else mfma_tile_128_i8<kElemI8, false>(a, lds, ch, 0, I, J);
+    } else {
+      mfma_tile_any<kElemI8, BT>(a, lds, ch, 0, I, J);
+    }
+    __threadfence();   // this thread's part of the tile is visible device-wide
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint32_t old = __hip_atomic_fetch_add(q.done + (size_t)slot * kServeLine, 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+      if ((uint64_t)old + 1 == job.base + (uint64_t)a.n_items) {
+        __threadfence_system();
+        __hip_atomic_store(job.flag, job.flag_value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+  }
 }
 
 hipError_t launch_xeng_mfma(const XArgs& a, int elem, int bt, hipStream_t s) {
@@ -877,6 +1126,8 @@ hipError_t launch_xeng_mfma(const XArgs& a, int elem, int bt, hipStream_t s) {
 #define CORR_LAUNCH_W2(EK) hipLaunchKernelGGL((xeng_mfma_128_kernel<EK>), g, b, 0, s, a)
   if (elem == kElemI8) {
     if (bt == 128) CORR_LAUNCH_W2(kElemI8); else CORR_LAUNCH(kElemI8, 64);
+  } else if (elem == kElemCI4) {
+    CORR_LAUNCH_W2(kElemCI4);   // 128-row tiles only
   } else if (elem == kElemF16) {
     if (bt == 128) CORR_LAUNCH_W2(kElemF16); else CORR_LAUNCH(kElemF16, 64);
   } else {
@@ -885,6 +1136,21 @@ hipError_t launch_xeng_mfma(const XArgs& a, int elem, int bt, hipStream_t s) {
 #undef CORR_LAUNCH
 #undef CORR_LAUNCH_W2
   return hipGetLastError();
+}
+
+hipError_t launch_xeng_serve(const ServeQueue& q, int bt, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  if (bt == 128) hipLaunchKernelGGL(xeng_serve_kernel<128>, dim3((unsigned)grid), dim3(256), 0, s, q);
+  else hipLaunchKernelGGL(xeng_serve_kernel<64>, dim3((unsigned)grid), dim3(256), 0, s, q);
+  return hipGetLastError();
+}
+
+int serve_blocks_per_cu(int bt) {
+  int n = 0;
+  const hipError_t e = bt == 128
+                           ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, xeng_serve_kernel<128>, 256, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, xeng_serve_kernel<64>, 256, 0);
+  return e == hipSuccess ? n : 0;
 }
 
 }  // namespace corr

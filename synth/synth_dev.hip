@@ -98,10 +98,11 @@ struct JobFill {
 }  // namespace
 
 // Fill callback for the serving scheduler: job `job_id` gets the ci8 signal
-// of seed base_seed + job_id (user points to a JobFill).  Queues one kernel on
+// of seed base_seed + job_id in rows of row_stride samples (user points to a
+// JobFill).  Queues one kernel on
 // `stream`; never blocks.
 extern "C" void synth_fill_job(void* user, uint64_t job_id, void* d_samples, int64_t n_ch, int64_t n_in,
-                               int64_t n_t, void* stream) {
+                               int64_t n_t, int64_t row_stride, void* stream) {
   const JobFill* f = static_cast<const JobFill*>(user);
-  synth_fill_ci8(d_samples, 0, n_ch, n_in, n_t, n_t, f->base_seed + job_id, &f->th, stream);
+  synth_fill_ci8(d_samples, 0, n_ch, n_in, n_t, row_stride, f->base_seed + job_id, &f->th, stream);
 }
