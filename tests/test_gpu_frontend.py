@@ -4,8 +4,12 @@ capture streams (Sec. 3), the complex F-stage on 5+5-bit words and on the
 (64 inputs, 1.28 MHz complex samples, 128 channels) through the X-engine.
 
 As for the real F-stage, the GPU transforms in FP32 and the oracle in FP64:
-the spectra error is bounded, requantised codes may differ only inside the
-tie band, and the X-engine must be bit-exact on the GPU's own ring.
+the spectra error is bounded (also by the a-priori FP32 FFT bound),
+requantised codes may differ only inside the tie band (their fraction is
+reported), and the X-engine must be bit-exact on the GPU's own ring
+(tests/fcheck.py).  The expected spectra are the oracle's DFT of the oracle's
+decode of the very words or bytes the GPU read; that decode is checked
+separately against the generator's levels.
 """
 import sys
 
@@ -13,6 +17,7 @@ import numpy as np
 import pytest
 import torch
 
+import fcheck
 import oracle
 import synth
 from paper_0906_1887_amd import CORR_DUMP_INTEG, CorrError, Correlator, aggregate_w16
@@ -32,17 +37,20 @@ def fe(n_in, ring, fmt):
                       device=DEV, volt_format=fmt)
 
 
-def check(levels, dbg, q_gpu, n_in):
-    """levels: int8 [n_blocks*128][n_in][2]; dbg: [128][n_in][nb][2]; q_gpu: [128][n_in][nb][2]."""
+def check(levels, dbg, q_gpu, n_in, label=""):
+    """levels: int8 [n_blocks*128][n_in][2], the oracle's decode of the words or
+    bytes the GPU read; dbg: [128][n_in][nb][2]; q_gpu: [128][n_in][nb][2]."""
     X = oracle.dft_complex(levels, 128)
-    rms = np.sqrt(np.mean(X ** 2))
-    err = np.abs(dbg.astype(np.float64) - X)
-    assert err.max() <= 1e-5 * rms, err.max() / rms
-    q_or = oracle.requant(X, S, 7)
-    y = S * X
-    tie = np.abs(y - np.floor(y) - 0.5) < 2.0 * S * err.max()
-    mism = q_or != q_gpu
-    assert not np.any(mism & ~tie), int(np.sum(mism & ~tie))
+    fcheck.check_spectra_requant(X, dbg, q_gpu, S, 7, fcheck.complex_bound(levels, 128), label)
+
+
+def decoded(raw_cpu: np.ndarray, fmt: str, lv: np.ndarray) -> np.ndarray:
+    """The oracle's decode of the raw words (cw16) or bytes (cb8) handed to the
+    GPU, checked against the generator's levels (a separate check: the
+    expected spectra come from the decode, not from the generator)."""
+    d = oracle.unpack_w16(raw_cpu.view(np.uint16)) if fmt == "cw16" else oracle.unpack_b8(raw_cpu.view(np.uint8))
+    assert np.array_equal(d, lv), fmt
+    return d
 
 
 def test_aggregate_bit_exact_and_counters():
@@ -113,12 +121,12 @@ def test_complex_fstage_shapes(fmt):
             dbg = torch.empty((128, n_in, nb, 2), dtype=torch.float32, device=DEV)
             c.channelise(raw, first_seq=seq, spectra_dbg=dbg)
             seq += nb
-            parts.append((lv, dbg.cpu().numpy()))
+            parts.append((decoded(raw.cpu().numpy(), fmt, lv), dbg.cpu().numpy()))
         q = c.ring_read().numpy()
         t0 = 0
         for lv, dbg in parts:
             nb = dbg.shape[2]
-            check(lv, dbg, q[:, :, t0:t0 + nb], n_in)
+            check(lv, dbg, q[:, :, t0:t0 + nb], n_in, f"{fmt} n_in={n_in}")
             t0 += nb
         c.correlate(None)
         out, n, exact = c.dump(CORR_DUMP_INTEG, device_out=False)
@@ -157,7 +165,8 @@ def test_prototype_one_second():
     c.channelise(agg[:64 * 128].contiguous(), first_seq=0, spectra_dbg=dbg)
     c.channelise(agg[64 * 128:].contiguous(), first_seq=64)
     q = c.ring_read().numpy()
-    check(lv[:64 * 128], dbg.cpu().numpy(), q[:, :, :64], n_in)
+    # expected spectra from the oracle's decode of the aggregated words the F-stage read
+    check(decoded(want, "cw16", lv[:64 * 128]), dbg.cpu().numpy(), q[:, :, :64], n_in, "prototype")
     c.correlate(None)
     out, n, exact = c.dump(CORR_DUMP_INTEG, device_out=False)
     assert n == nb and exact

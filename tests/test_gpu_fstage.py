@@ -3,9 +3,10 @@ and of the full FX path with the FP64 long-run accumulator, through the C ABI.
 
 Requantisation: the GPU transforms in FP32 and the oracle in FP64, so a
 value within the FFT's rounding error of a .5 boundary may round either way.
-The test (i) bounds the spectra error, (ii) allows requantised mismatches only
-inside that tie band, and (iii) requires the X-engine to be bit-exact on the
-GPU's own requantised spectra.
+The test (i) bounds the spectra error (by 1e-5 of the channel RMS and by the
+a-priori FP32 FFT bound), (ii) allows requantised mismatches only inside that
+tie band and reports their fraction (tests/fcheck.py), and (iii) requires the
+X-engine to be bit-exact on the GPU's own requantised spectra.
 """
 import math
 import sys
@@ -14,6 +15,7 @@ import numpy as np
 import pytest
 import torch
 
+import fcheck
 import oracle
 import synth
 from paper_0906_1887_amd import (CORR_DUMP_FOLD, CORR_DUMP_INTEG, CORR_DUMP_LONGRUN, CorrError,
@@ -34,20 +36,10 @@ def fx(n_in, ring, longrun=False):
                       fp64_longrun=longrun, device=DEV)
 
 
-def check_spectra_and_requant(v, dbg, q_gpu, n_in):
+def check_spectra_and_requant(v, dbg, q_gpu, n_in, label=""):
     X = oracle.dft_real(v, 256)                                   # [128][n_in][nb][2] FP64
-    Xg = dbg.astype(np.float64)
-    rms = np.sqrt(np.mean(X ** 2))
-    err = np.abs(Xg - X)
-    assert err.max() <= 1e-5 * rms, err.max() / rms
-    q_or = oracle.requant(X, S, 7)
-    y = S * X
-    delta = 2.0 * S * err.max()
-    frac = np.abs(y - np.floor(y) - 0.5)                          # distance to a .5 boundary
-    tie = frac < delta
-    mism = q_or != q_gpu
-    assert not np.any(mism & ~tie), int(np.sum(mism & ~tie))
-    return int(mism.sum()), mism.size
+    r = fcheck.check_spectra_requant(X, dbg, q_gpu, S, 7, fcheck.real_bound(v, 256), label)
+    return r["mismatch_frac"]
 
 
 def test_fstage_small_and_x_on_gpu_spectra():
@@ -68,7 +60,7 @@ def test_fstage_small_and_x_on_gpu_spectra():
         t0 = 0
         for v, dbg in vs:
             nb = dbg.shape[2]
-            check_spectra_and_requant(v, dbg, q[:, :, t0:t0 + nb], n_in)
+            check_spectra_and_requant(v, dbg, q[:, :, t0:t0 + nb], n_in, f"n_in={n_in}")
             t0 += nb
         c.correlate(None)
         out, n, exact = c.dump(CORR_DUMP_INTEG, device_out=False)
@@ -89,7 +81,7 @@ def test_fstage_wide_launches_every_block():
         dbg = torch.empty((128, n_in, nb, 2), dtype=torch.float32, device=DEV)
         c.channelise(torch.from_numpy(v).to(DEV), first_seq=0, spectra_dbg=dbg)
         q = c.ring_read().numpy()
-        check_spectra_and_requant(v, dbg.cpu().numpy(), q[:, :, :nb], n_in)
+        check_spectra_and_requant(v, dbg.cpu().numpy(), q[:, :, :nb], n_in, f"blocks={nb}")
         c.close()
 
 
@@ -141,7 +133,7 @@ def test_c2_full_fx_longrun():
         if d in (0, n_dump - 1):
             q = c.ring_read().numpy()
             if d == 0:
-                check_spectra_and_requant(v[: 64 * 256], dbg.cpu().numpy(), q[:, :, :64], n_in)
+                check_spectra_and_requant(v[: 64 * 256], dbg.cpu().numpy(), q[:, :, :64], n_in, "C2")
         c.correlate(None)
         out, n, exact = c.dump(CORR_DUMP_INTEG | CORR_DUMP_FOLD, device_out=False)
         assert n == nb and exact

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 import torch
 
+import fcheck
 import oracle
 import synth
 from paper_0906_1887_amd import CORR_DUMP_INTEG, Correlator
@@ -45,12 +46,7 @@ def test_fstage_hundreds_of_inputs():
     c.channelise(torch.from_numpy(v).to(DEV), first_seq=0, spectra_dbg=dbg)
     q = c.ring_read().numpy()
     X = oracle.dft_real(v, 256)
-    err = np.abs(dbg.cpu().numpy().astype(np.float64) - X)
-    rms = np.sqrt(np.mean(X ** 2))
-    assert err.max() <= 1e-5 * rms
-    y = s_real * X
-    tie = np.abs(y - np.floor(y) - 0.5) < 2.0 * s_real * err.max()
-    assert not np.any((oracle.requant(X, s_real, 7) != q) & ~tie)
+    fcheck.check_spectra_requant(X, dbg.cpu().numpy(), q, s_real, 7, fcheck.real_bound(v, 256), "real n_in=512")
     c.close()
 
     s_cplx = float(np.float32(1.0 / 16.0))
@@ -63,13 +59,12 @@ def test_fstage_hundreds_of_inputs():
     dbg = torch.empty((128, n_in, nb, 2), dtype=torch.float32, device=DEV)
     c.channelise(raw, first_seq=0, spectra_dbg=dbg)
     q = c.ring_read().numpy()
-    X = oracle.dft_complex(lv, 128)
-    err = np.abs(dbg.cpu().numpy().astype(np.float64) - X)
-    rms = np.sqrt(np.mean(X ** 2))
-    assert err.max() <= 1e-5 * rms
-    y = s_cplx * X
-    tie = np.abs(y - np.floor(y) - 0.5) < 2.0 * s_cplx * err.max()
-    assert not np.any((oracle.requant(X, s_cplx, 7) != q) & ~tie)
+    # expected spectra from the oracle's decode of the words the GPU read
+    lvd = oracle.unpack_w16(np.ascontiguousarray(rec[0, :, 1:]))
+    assert np.array_equal(lvd, lv)
+    X = oracle.dft_complex(lvd, 128)
+    fcheck.check_spectra_requant(X, dbg.cpu().numpy(), q, s_cplx, 7, fcheck.complex_bound(lvd, 128),
+                                 "complex n_in=256")
     c.correlate(None)
     out, n, exact = c.dump(CORR_DUMP_INTEG, device_out=False)
     assert n == nb and exact

@@ -2,7 +2,9 @@
 spectral leakage suggested as further work) through the C ABI: 4 taps of 256
 points, Hamming-windowed sinc prototype; consecutive corr_channelise calls
 overlap by the 3 blocks of history.  Same three checks as the plain F-stage
-(spectra error bound, tie-band requantiser, X bit-exact on the GPU's ring),
+(spectra error bound incl. the a-priori FP32 bound of the weighted sum and
+FFT, tie-band requantiser with its mismatch fraction, X bit-exact on the
+GPU's ring; tests/fcheck.py),
 then the leakage of a tone between channel centres, against a plain-FFT plan.
 """
 import math
@@ -12,6 +14,7 @@ import numpy as np
 import pytest
 import torch
 
+import fcheck
 import oracle
 import synth
 from paper_0906_1887_amd import CORR_DUMP_INTEG, CorrError, Correlator
@@ -48,15 +51,8 @@ def test_pfb_parity_with_history_overlap():
             b0 += nb
         q = c.ring_read().numpy()
         X = oracle.pfb_real(v, 256, P)                                  # [128][n_in][total][2]
-        Xg = np.concatenate(dbgs, axis=2).astype(np.float64)
-        rms = np.sqrt(np.mean(X ** 2))
-        err = np.abs(Xg - X)
-        say(f"[pfb] spectra max error / rms = {err.max() / rms:.2e}")
-        assert err.max() <= 1e-5 * rms
-        q_or = oracle.requant(X, S, 7)
-        y = S * X
-        tie = np.abs(y - np.floor(y) - 0.5) < 2.0 * S * err.max()
-        assert not np.any((q_or != q) & ~tie)
+        Xg = np.concatenate(dbgs, axis=2)
+        fcheck.check_spectra_requant(X, Xg, q, S, 7, fcheck.pfb_bound(v, 256, P), f"pfb n_in={n_in}")
         c.correlate(None)
         out, n, exact = c.dump(CORR_DUMP_INTEG, device_out=False)
         assert n == total and exact

@@ -1,6 +1,9 @@
 """Serving scheduler on the GPU through the C ABI: each job's result is the
 same alone and inside a concurrent mix (bit-exact, integer data), matches the
-oracle, and admission by HBM footprint queues jobs that do not fit."""
+oracle, and admission by HBM footprint queues jobs that do not fit.  Jobs
+with 16-byte aligned rows run on the device job queue (persistent grids, no
+per-job plan or launch); results land in device or pinned host buffers;
+caller buffers with an odd row stride take the per-job plan path."""
 import sys
 import time
 
@@ -53,11 +56,11 @@ def run_jobs(jobs, concurrent, arena_bytes=8 << 30, n_streams=4):
             outs.append(out)
             ids.append(jid)
             if not concurrent:
-                st, n, ta, td = wait(s, jid)
+                st, n, ta, td, tv = wait(s, jid)
                 assert st == 0 and n == T
         if concurrent:
             for jid, (n_in, n_ch, T) in zip(ids, jobs):
-                st, n, ta, td = wait(s, jid)
+                st, n, ta, td, tv = wait(s, jid)
                 assert st == 0 and n == T
         stats = s.stats()
     finally:
@@ -99,9 +102,19 @@ def test_admission_queues_when_arena_is_small():
     fn, user, keep = synth.DeviceGen().job_fill(BASE_SEED)
     s = Scheduler(64 << 20, 2)
     try:
-        with pytest.raises(CorrError) as e:               # footprint beyond the whole arena
-            s.submit(1024, 768, 8000, result_buf(1, 1), fill=fn, fill_user=user)
+        # footprint beyond the whole arena: refused at submission, before the
+        # result buffer is touched (the raw C call; the Python wrapper would
+        # already refuse the one-element buffer)
+        j = _lib.corr_job_desc()
+        j.n_inputs, j.n_channels, j.n_samples, j.max_abs = 1024, 768, 8000, 7
+        j.fill, j.fill_user = fn, user
+        j.dst = result_buf(1, 1).data_ptr()
+        j.dst_is_device = 1
+        with pytest.raises(CorrError) as e:
+            _lib.corr_sched_submit(s.handle, j, _lib.corr_sched_now())
         assert e.value.status == _lib.CORR_E_WORKSPACE
+        with pytest.raises(AssertionError):               # the wrapper checks the buffer size
+            s.submit(1024, 768, 8000, result_buf(1, 1), fill=fn, fill_user=user)
     finally:
         s.close()
     del keep
@@ -115,7 +128,7 @@ def test_caller_device_samples_and_host_result():
     s = Scheduler(64 << 20, 2)
     try:
         jid = s.submit(n_in, n_ch, T, out, d_samples=xt.data_ptr())
-        st, n, ta, td = wait(s, jid)
+        st, n, ta, td, tv = wait(s, jid)
         assert st == 0 and n == T and td >= ta
     finally:
         s.close()
@@ -136,8 +149,70 @@ def test_caller_ring_with_row_stride():
             s.submit(n_in, n_ch, T, out, d_samples=rt.data_ptr(), row_stride=T - 1)
         assert e.value.status == _lib.CORR_E_INVAL
         jid = s.submit(n_in, n_ch, T, out, d_samples=rt.data_ptr(), row_stride=stride)
-        st, n, ta, td = wait(s, jid)
+        st, n, ta, td, tv = wait(s, jid)
         assert st == 0 and n == T
     finally:
         s.close()
     assert np.array_equal(out.cpu().numpy().astype(np.int64), oracle.xengine_ci8(x))
+
+
+def test_queue_host_and_device_destinations_alone_equals_mix():
+    """The device job queue with results copied to pinned host memory and
+    written straight to device memory, jobs of both tile sizes submitted
+    together (a large job first, small ones behind it): every result equals
+    the same job run alone, and the oracle; the device-complete time precedes
+    the host landing."""
+    jobs = [(520, 256, 1000), (16, 64, 1000), (100, 3, 77), (64, 128, 2000), (200, 7, 64), (17, 1, 1)]
+    gen = synth.DeviceGen()
+    fn, user, keep = gen.job_fill(BASE_SEED)
+    results = {}
+    for mode in ("alone", "mix"):
+        s = Scheduler(4 << 30, 2)
+        outs, ids = [], []
+        try:
+            for k, (n_in, n_ch, T) in enumerate(jobs):
+                host = k % 2 == 0
+                out = result_buf(n_in, n_ch, device=not host)
+                if host:
+                    out = out.pin_memory()
+                jid = s.submit(n_in, n_ch, T, out, fill=fn, fill_user=user)
+                outs.append(out)
+                ids.append(jid)
+                if mode == "alone":
+                    st, n, ta, td, tv = wait(s, jid)
+                    assert st == 0 and n == T and ta <= tv <= td
+            if mode == "mix":
+                for jid, (n_in, n_ch, T) in zip(ids, jobs):
+                    st, n, ta, td, tv = wait(s, jid)
+                    assert st == 0 and n == T and ta <= tv <= td
+            stats = s.stats()
+        finally:
+            s.close()
+        assert stats["completed"] == len(jobs) and stats["failed"] == 0
+        results[mode] = (ids, [o.cpu().numpy() for o in outs])
+        say(f"[serving queue] {mode} done")
+    del keep
+    ids_a, alone = results["alone"]
+    ids_m, mix = results["mix"]
+    for k, (n_in, n_ch, T) in enumerate(jobs):
+        assert np.array_equal(alone[k], mix[k]), k
+        x = synth.ci8(BASE_SEED + ids_m[k], n_ch, n_in, T)
+        assert np.array_equal(mix[k].astype(np.int64), oracle.xengine_ci8(x)), k
+
+
+def test_odd_row_stride_takes_the_plan_path():
+    """Caller rows whose stride is not a multiple of 8 samples (not 16-byte
+    aligned) are correlated through a per-job plan; the result is the same."""
+    n_in, n_ch, T, stride = 70, 3, 500, 1001
+    ring = synth.ci8(93, n_ch, n_in, stride)
+    x = np.ascontiguousarray(ring[:, :, :T])
+    rt = torch.from_numpy(ring).to(DEV)
+    out = result_buf(n_in, n_ch, device=False).pin_memory()
+    s = Scheduler(64 << 20, 2)
+    try:
+        jid = s.submit(n_in, n_ch, T, out, d_samples=rt.data_ptr(), row_stride=stride)
+        st, n, ta, td, tv = wait(s, jid)
+        assert st == 0 and n == T
+    finally:
+        s.close()
+    assert np.array_equal(out.numpy().astype(np.int64), oracle.xengine_ci8(x))

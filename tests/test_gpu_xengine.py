@@ -23,9 +23,9 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu_vis(x, engine, sample_type="ci8", chunks=None):
+def gpu_vis(x, engine, sample_type="ci8", chunks=None, max_abs=7):
     n_ch, n_in, T, _ = x.shape
-    c = Correlator(n_in, n_ch, engine=engine, sample_type=sample_type, max_abs=7, device=DEV)
+    c = Correlator(n_in, n_ch, engine=engine, sample_type=sample_type, max_abs=max_abs, device=DEV)
     if sample_type == "ci8":
         xt = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
         esz = 2
@@ -89,6 +89,93 @@ def test_extreme_values_i8():
     for engine in ("i8", "fp32"):
         say(f"[xengine {engine}] extremes")
         assert np.array_equal(gpu_vis(x, engine), oracle.xengine_ci8(x))
+
+
+def full_range(seed, n_ch, n_in, T):
+    """Integers uniform in [-127, 127] (the whole declared int8 range), with
+    inputs 0..3 pinned at the extremes (+-127 in both parts, all four sign
+    patterns) so that their autos reach 2 * 127^2 * T."""
+    rng = np.random.default_rng(seed)
+    x = rng.integers(-127, 128, size=(n_ch, n_in, T, 2)).astype(np.int8)
+    for k, (a, b) in enumerate(((127, 127), (-127, 127), (127, -127), (-127, -127))):
+        if k < n_in:
+            x[:, k, :, 0] = a
+            x[:, k, :, 1] = b
+    return x
+
+
+@pytest.mark.parametrize("engine", ["i8", "fp32"])
+def test_full_int8_range_near_bounds(engine):
+    """max_abs = 127 (the largest declared range): the byte rotation of the
+    int8 engine on large magnitudes and sums close to the exactness bounds,
+    2 * 127^2 * T <= 2^31 - 1 (int32, T <= 66572) and <= 2^24 (FP32 on integer
+    data, T <= 520).  16-byte aligned rows (T a multiple of 8) take the
+    matrix-core kernel with its LDS-staged loads, odd T the register-staged
+    int8 kernel; N_I = 130 has a diagonal and an off-diagonal 128-row tile
+    with a ragged last panel, N_I = 61 the 64-row engine (both split K)."""
+    shapes = ((130, 66568), (61, 66571), (130, 66571)) if engine == "i8" else ((130, 520), (61, 517), (130, 519))
+    for n_in, T in shapes:
+        say(f"[xengine {engine}] max_abs=127 n_in={n_in} T={T}")
+        x = full_range(n_in * 7 + T, 1, n_in, T)
+        want = oracle.xengine_ci8(x)
+        d = oracle.baseline_index(np.arange(4), np.arange(4))
+        assert want[0, d, 0].max() == 2 * 127 * 127 * T          # the bound itself is reached
+        got = gpu_vis(x, engine, max_abs=127)
+        assert np.array_equal(got, want), (engine, n_in, T)
+    if engine == "i8":
+        # many channels (>= 1024 tiles: one pass, no K split) at the full range
+        say("[xengine i8] max_abs=127 n_in=150 n_ch=350 T=1000 (no K split)")
+        x = full_range(3, 350, 150, 1000)
+        assert np.array_equal(gpu_vis(x, "i8", max_abs=127), oracle.xengine_ci8(x))
+
+
+def test_aligned_calls_accumulate_in_the_epilogue():
+    """Two 16-byte aligned corr_correlate calls into one integration with no K
+    split: the second pass adds its tile into the accumulator in the
+    read-modify-write epilogue of the 128-row int8 matrix-core kernel.  One
+    channel of N_I = 200 with 128-sample calls (too few samples to split), and
+    350 channels of N_I = 150 (>= 1024 tiles), against one call and the
+    oracle."""
+    for n_ch, n_in, T in ((1, 200, 256), (350, 150, 1024)):
+        say(f"[xengine i8] aligned chunks n_ch={n_ch} n_in={n_in} T={T}")
+        x = full_range(n_in + T, n_ch, n_in, T)
+        want = oracle.xengine_ci8(x)
+        half = T // 2
+        assert (half * 2) % 16 == 0 and (T * 2) % 16 == 0
+        got = gpu_vis(x, "i8", chunks=[(0, half), (half, T)], max_abs=127)
+        one = gpu_vis(x, "i8", max_abs=127)
+        assert np.array_equal(one, want)
+        assert np.array_equal(got, want)
+
+
+def test_team_schedule_shapes():
+    """Arrays of 5 to 11 row panels of 128 inputs with enough tiles (>= 1024,
+    so that K is not split) run on
+    the team schedule (persistent grid, one workgroup per off-diagonal tile,
+    diagonal tiles from a queue): 640 inputs (5 panels, three teams per XCD),
+    1000 (8 panels, a ragged last one; 33 channels, unevenly split over the
+    XCDs) and 1100 (9 panels, one team).  Then the same launch with the waits
+    switched off and with a slack of two steps: the waits only shape the
+    timing, so every result must stay bit-exact."""
+    import os
+    for n_in, n_ch, T in ((640, 72, 200), (1000, 33, 136), (1100, 16, 72)):
+        say(f"[xengine i8 team] n_in={n_in} n_ch={n_ch} T={T}")
+        x = synth.ci8(seed=n_in + n_ch + T, n_channels=n_ch, n_inputs=n_in, n_samples=T)
+        want = oracle.xengine_ci8(x)
+        assert np.array_equal(gpu_vis(x, "i8"), want), (n_in, n_ch, T)
+        if n_in == 1000:
+            for env in ({"CORR_TEAM_SPIN": "0"}, {"CORR_TEAM_SLACK": "2"}, {"CORR_TEAM": "0"}):
+                say(f"[xengine i8 team] n_in={n_in} {env}")
+                old = {k: os.environ.get(k) for k in env}
+                os.environ.update(env)
+                try:
+                    assert np.array_equal(gpu_vis(x, "i8"), want), env
+                finally:
+                    for k, v in old.items():
+                        if v is None:
+                            os.environ.pop(k, None)
+                        else:
+                            os.environ[k] = v
 
 
 def test_chunked_calls_equal_one_call():

@@ -175,3 +175,35 @@ def test_longrun_fold_exact(seed):
         oracle.fold(L, d)
     exact = sum(d.astype(object) for d in dumps)
     assert all(int(a) == b for a, b in zip(L.ravel(), exact.ravel()))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_longrun_fold_f64_exact_dyadic(seed):
+    """FP64 fold of float dumps (the FP32/FP16/FP8 engines' accumulators):
+    dyadic values with at most 40 significant bits between 2^-20 and 2^20, so
+    every partial sum of 10 is representable and the fold must equal the exact
+    rational sum (Fig. 1: L += V after each read-out)."""
+    from fractions import Fraction
+    rng = np.random.default_rng(seed)
+    dumps = [rng.integers(-(2 ** 40), 2 ** 40, size=(3, 10, 2)).astype(np.float64) * 2.0 ** -20
+             for _ in range(10)]
+    L = np.zeros((3, 10, 2))
+    for d in dumps:
+        oracle.fold(L, d)
+    exact = [sum(Fraction(float(d.flat[k])) for d in dumps) for k in range(L.size)]
+    assert all(Fraction(float(a)) == b for a, b in zip(L.ravel(), exact))
+
+
+def test_longrun_fold_f64_rounds_each_step():
+    """Each fold is one IEEE FP64 addition, rounded to nearest even: 1 + 2^-53
+    is a tie that rounds back to 1, twice, although the exact sum 1 + 2^-52 is
+    representable; and a fold of -L gives exactly +0."""
+    L = np.array([1.0, 3.5])
+    for _ in range(2):
+        oracle.fold(L, np.array([2.0 ** -53, 0.0]))
+    assert L[0] == 1.0
+    oracle.fold(L, np.array([-1.0, -3.5]))
+    assert L[0] == 0.0 and L[1] == 0.0 and not np.signbit(L[0])
+    L = np.array([1.0])
+    oracle.fold(L, np.array([3 * 2.0 ** -53]))                    # 1 + 1.5 ulp -> 1 + 2 ulp
+    assert L[0] == 1.0 + 2.0 ** -51
