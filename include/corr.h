@@ -121,7 +121,16 @@ typedef struct {
     int32_t fp64_longrun;     /* nonzero: keep an FP64 long-run accumulator  */
     int64_t ring_samples;     /* F-stage: ring capacity in time samples per
                                  channel (one sample per FFT block).
-                                 F16/F8: conversion chunk in samples.        */
+                                 F16/F8: > 0 = convert each call in chunks of
+                                 at most this many samples into a staging
+                                 buffer, then correlate the chunk; 0 = no
+                                 staging buffer: the X-engine converts while
+                                 it loads (one pass over the CF32 samples;
+                                 rows must start 8-byte aligned, else
+                                 corr_correlate returns CORR_E_UNSUPPORTED;
+                                 F8 scales s_c by the call's samples).  Both
+                                 give the same sums when a chunk holds the
+                                 whole call.                                 */
     int32_t volt_format;      /* corr_volt_t of corr_channelise's input (0
                                  when fft_size is 0)                         */
     int32_t pfb_taps;         /* real F-stage only: 0 or 1 = plain DFT; P > 1
@@ -261,7 +270,9 @@ corr_status corr_correlate(corr_plan *plan, const void *d_samples, int64_t n_sam
  * if dst_is_device == 0, else device), then reset the integration
  * accumulator and its sample count unless NO_RESET.  Raw sums are returned;
  * dividing by *n_samples_out is the caller's choice.  Synchronises the
- * plan's stream, so device faults surface here as CORR_E_HIP.
+ * plan's stream, so device faults surface here as CORR_E_HIP -- except for a
+ * plain reset (no INTEG, LONGRUN or FOLD flag), which queues nothing and
+ * returns at once.
  * *n_samples_out: time samples accumulated in the integration (before reset).
  * *exact_out: 1 if every sum copied to dst is provably exact, else 0: for
  * INTEG, integer samples on the int8 or FP32 engine (within the bounds
@@ -282,7 +293,8 @@ corr_status corr_ring_read(corr_plan *plan, void *dst, int32_t dst_is_device, in
  * bytes), n = *n_samples_out, and, if scales != NULL, the per-channel FP8
  * scales s_c (1 for FP16) to host scales[n_channels].  dst must hold
  * n_channels * n_inputs * ring_samples * 2 elements.  For parity tests of the
- * conversion.  Synchronises the plan's stream. */
+ * conversion.  Synchronises the plan's stream.  CORR_E_STATE for a plan
+ * with ring_samples == 0 (nothing is staged). */
 corr_status corr_stage_read(corr_plan *plan, void *dst, float *scales, int64_t *n_samples_out);
 
 /* Bytes of one integration dump (what = CORR_DUMP_INTEG) or long-run dump. */
@@ -297,13 +309,16 @@ corr_status corr_dump_bytes(const corr_plan *plan, int32_t what, size_t *bytes);
  * queue until its HBM footprint fits in the caller's arena (its samples when
  * a fill callback produces them, its result when the destination is host
  * memory) and one of 64 queue slots is free.  An admitted job is published
- * on a job queue in the arena's head; persistent int8 X-engine grids (one for
- * arrays of more than 64 inputs, one for the rest) take work items --
- * (channel, baseline tile) pairs -- round robin from every published job, so
+ * on a job queue in the arena's head; a persistent int8 X-engine grid (as
+ * many workgroups as the GPU holds at once) takes work items -- (channel,
+ * 128-row baseline tile) pairs -- round robin from every published job, so
  * jobs that arrive while others run are taken up by the grid already on the
  * device, and their work overlaps.  No per-job plan is created and no kernel
- * is launched per job; a new grid is launched only when work is published
- * and none is running.  The job's device result is complete when its last
+ * is launched per job: the grid closes as a whole once the queue has been
+ * idle for 0.1 ms, and a new one is launched when work is published after
+ * that.  While a grid runs it holds every CU, so other work on the GPU (the
+ * per-job path below, fill callbacks) waits for the queue to drain.  The
+ * job's device result is complete when its last
  * item is done (the grid then writes a completion word in pinned host memory
  * that the scheduler polls); a host destination then receives a copy, and
  * the job is complete when that copy has landed (the latency end point).

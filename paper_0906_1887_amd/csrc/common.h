@@ -18,6 +18,8 @@ constexpr int kElemI8 = 0;
 constexpr int kElemF16 = 1;
 constexpr int kElemF8 = 2;
 constexpr int kElemCI4 = 3;   // int8 engine on 4-bit complex samples, one byte each
+constexpr int kElemF16Cvt = 4;  // FP16 engine converting complex float32 as it stages
+constexpr int kElemF8Cvt = 5;   // FP8 engine converting (with the per-channel scale) as it stages
 
 __device__ __forceinline__ int64_t xcd_item(int64_t bid, int64_t per_xcd) {
   const int64_t xcd = bid % kNumXcd;
@@ -53,37 +55,72 @@ struct XArgs {
   int32_t n_items;          // n_ch * n_tiles * n_split
   int32_t per_xcd;          // ceil(n_items / 8)
   int32_t accumulate;       // 1: out += tile; 0: out = tile
-  int32_t pad_;
+  int32_t order;            // 1: off-diagonal tiles first within each XCD (item_decode)
   const float* inv_scale2;  // FP8: per-channel 1/s_c^2 applied in the epilogue (else null)
+  const uint32_t* m_bits;   // converting FP8 engine: per-channel max |re|, |im| (float bits)
 };
 
-// Team schedule of the 128-row int8 engine (xeng_team_kernel).  Sync words
-// (uint32, zero at launch): per XCD, one per team plus the diagonal-tile
-// queue, each on its own 128-byte line.
-constexpr int kTeamSyncLine = 32;                  // uint32 per line
-constexpr int kTeamSyncStride = 4 * kTeamSyncLine; // per XCD: up to 3 teams + queue
-struct TeamArgs {
-  XArgs x;
-  uint32_t* sync;           // [kNumXcd][kTeamSyncStride]
-  int32_t nb;               // row panels of 128 inputs
-  int32_t n_full;           // off-diagonal tiles per channel = workgroups per team
-  int32_t teams;            // teams per XCD (1..3)
-  int32_t slack;            // steps a member may start ahead of its team's slowest
-  int32_t spin_limit;       // polls before a member stops waiting
-  int32_t pad_;
-};
+// Work item -> (channel, K split, tile I >= J) of the matrix-core engines.
+// order 0: tile fastest, then split, then channel.  order 1 (a pass without a
+// K split whose channels divide evenly over the XCDs, so that each XCD's
+// contiguous item range holds whole channels): each XCD first runs the
+// off-diagonal tiles of its channels, channel by channel, then their
+// diagonal tiles.  Workgroups resident together then run tiles of the same
+// length and stay close in K, so the row panels their tiles share are still
+// in the XCD's L2 when the second reader arrives; in the plain order the
+// shorter diagonal tiles (a quarter of their blocks is skipped) let the
+// starts drift apart.
+__device__ __forceinline__ void item_decode(const XArgs& a, int64_t item, int& ch, int& split, int& I, int& J) {
+  if (a.order == 1) {
+    int nb1, unused;
+    tile_decode(a.n_tiles - 1, nb1, unused);   // the last tile is (nb - 1, nb - 1)
+    const int nb = nb1 + 1;
+    const int n_off = a.n_tiles - nb;
+    const int64_t cpx = a.per_xcd / a.n_tiles;  // channels per XCD
+    const int64_t x = item / a.per_xcd, l = item % a.per_xcd;
+    split = 0;
+    if (l < cpx * n_off) {
+      ch = (int)(x * cpx + l / n_off);
+      tile_decode((int)(l % n_off), I, J);      // o = i(i+1)/2 + j, j <= i  ->  tile (i + 1, j)
+      I += 1;
+    } else {
+      const int64_t d = l - cpx * n_off;
+      ch = (int)(x * cpx + d / nb);
+      I = J = (int)(d % nb);
+    }
+    return;
+  }
+  const int tile = (int)(item % a.n_tiles);
+  const int64_t rest = item / a.n_tiles;
+  split = (int)(rest % a.n_split);
+  ch = (int)(rest / a.n_split);
+  tile_decode(tile, I, J);
+}
+
+// FP8 scale of a channel with max |re|, |im| = m: the largest power of two s
+// with s * m <= 448 (the largest finite E4M3 value); 1 when m is 0 or not
+// finite.  The exponent is kept in [-60, 60] (so 1/s^2 stays a normal float)
+// and the correction loops are bounded; within that range the result is
+// exact, because s is a power of two and the comparisons are exact.
+__device__ __forceinline__ float e4m3_scale(float m) {
+  if (!(m > 0.f) || !(m < INFINITY)) return 1.f;
+  const float e = fminf(fmaxf(floorf(log2f(448.f / m)), -60.f), 60.f);
+  float s = ldexpf(1.f, (int)e);
+  for (int k = 0; k < 4 && s * m > 448.f && s > 0x1p-60f; ++k) s *= 0.5f;
+  for (int k = 0; k < 4 && 2.f * s * m <= 448.f && s < 0x1p60f; ++k) s *= 2.f;
+  return s;
+}
 
 // Serving queue (xeng_serve_kernel).  The host publishes each admitted job
 // in a slot; the claim and done words of a slot count items over all the jobs
 // the slot has held and are never reset, so a job's items are the claim
-// values [base, base + n_items).
+// values [base, base + n_items).  Every job runs 128-row tiles.
 constexpr int kServeLine = 32;             // uint32 per 128-byte line
-constexpr int kServeSmall = 1 << 16;       // active-list flag: the slot's job has 64-row tiles
 struct ServeJob {
   XArgs x;                  // the job's pass: samples, strides, output, n_tiles, n_items (channel x tile)
   uint32_t* flag;           // completion word in host memory (device view)
   uint32_t flag_value;      // written there when the job's last item is done
-  int32_t bt;               // tile rows: 64 or 128
+  int32_t pad0_;
   uint64_t base;            // claim value of the job's first item
   uint64_t pad_[3];
 };
@@ -93,10 +130,14 @@ struct ServeQueue {
   uint64_t* claim;          // slot s at claim[s * kServeLine / 2]
   uint32_t* done;           // slot s at done[s * kServeLine]
   const int32_t* active;    // [1 + n_slots]: count, then the slots holding jobs
-                            // (| kServeSmall for 64-row jobs)
   uint32_t* rr;             // round-robin counter
+  uint64_t* last_claim;     // wall clock (s_memrealtime ticks) of the latest claim or grid start
+  uint32_t* closing;        // highest grid generation that has closed (no more claims)
+  uint32_t* host_closing;   // the same, in host memory (device view) for the scheduler
+  uint32_t gen;             // this launch's generation (increasing from 1)
+  uint32_t idle_ticks;      // queue idle this long (100 MHz ticks): the grid closes
   int32_t n_slots;
-  int32_t idle_polls;       // polls without work before a workgroup exits
+  int32_t max_polls;        // bound on one workgroup's empty polls (a safety net)
 };
 
 }  // namespace corr

@@ -15,7 +15,6 @@
 
 #include <cmath>
 #include <cstdio>
-#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -42,7 +41,6 @@ struct Layout {
   size_t pfb = 0, pfb_bytes = 0;       // filterbank coefficients (pfb_taps > 1)
   size_t stage = 0, stage_bytes = 0;   // FP16/FP8 staged samples
   size_t mbits = 0, scales = 0;        // FP8 per-channel max and 1/s^2
-  size_t sync = 0, sync_bytes = 0;     // team-schedule sync words (128-row engine)
   int64_t stage_stride = 0;            // staged samples per row
   int stage_sb = 0;                    // staged bytes per complex sample
   size_t total = 0;
@@ -69,7 +67,7 @@ corr_status validate(const corr_config* c) {
   if (c->engine == CORR_X_F16 || c->engine == CORR_X_F8) {
     // float samples staged to FP16 / FP8 in chunks of ring_samples
     if (c->sample_type != CORR_CF32 || c->max_abs != 0 || c->fft_size != 0) return CORR_E_INVAL;
-    if (c->ring_samples < 1) return CORR_E_INVAL;
+    if (c->ring_samples < 0) return CORR_E_INVAL;   // 0: convert while staging, no chunked staging buffer
     if (c->n_channels > 65535 || c->n_inputs > 65535) return CORR_E_UNSUPPORTED;
   }
   if (c->engine == CORR_X_I8) {
@@ -101,7 +99,9 @@ corr_status validate(const corr_config* c) {
 Layout layout_of(const corr_config* c) {
   Layout L;
   L.n_products = n_products(c->n_inputs);
-  L.bt = (c->n_inputs > 64 || c->sample_type == CORR_CI4) ? 128 : 64;   // CI4: 128-row tiles only
+  // CI4 and the converting FP16/FP8 engines run 128-row tiles only
+  const bool lowp_cvt = (c->engine == CORR_X_F16 || c->engine == CORR_X_F8) && c->ring_samples == 0;
+  L.bt = (c->n_inputs > 64 || c->sample_type == CORR_CI4 || lowp_cvt) ? 128 : 64;
   const int64_t nb = (c->n_inputs + L.bt - 1) / L.bt;
   L.n_tiles = (int)(nb * (nb + 1) / 2);
   const int64_t tiles_total = (int64_t)c->n_channels * L.n_tiles;
@@ -136,17 +136,12 @@ Layout layout_of(const corr_config* c) {
     L.stage_sb = (c->engine == CORR_X_F16) ? 4 : 2;
     L.stage_stride = (c->ring_samples + 63) / 64 * 64;
     L.stage = off;
-    L.stage_bytes = (size_t)c->n_channels * c->n_inputs * L.stage_stride * L.stage_sb;
+    L.stage_bytes = (size_t)c->n_channels * c->n_inputs * L.stage_stride * L.stage_sb;   // 0 when converting
     off = align_up(off + L.stage_bytes, kAlign);
     L.mbits = off;
     off = align_up(off + (size_t)c->n_channels * 4, kAlign);
     L.scales = off;
     off = align_up(off + (size_t)c->n_channels * 4, kAlign);
-  }
-  if (L.bt == 128) {
-    L.sync = off;
-    L.sync_bytes = (size_t)corr::kNumXcd * corr::kTeamSyncStride * sizeof(uint32_t);
-    off = align_up(off + L.sync_bytes, kAlign);
   }
   if (L.max_split > 1) {
     L.part = off;
@@ -186,74 +181,10 @@ corr_status hip_fail(corr_plan* p, hipError_t e) {
 
 void* at(corr_plan* p, size_t off) { return p->ws + off; }
 
-// CUs of the current device and team-kernel workgroups per CU (cached per
-// device; 0 if unknown).
-struct TeamHw {
-  int cus = -1, per_cu = 0;
-};
-TeamHw team_hw() {
-  static TeamHw cache[64];
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return TeamHw{0, 0};
-  TeamHw& h = cache[dev];
-  if (h.cus < 0) {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
-    h.per_cu = corr::team_blocks_per_cu();
-    h.cus = cus;
-  }
-  return h;
-}
-
-int env_int(const char* name, int dflt) {
-  const char* v = std::getenv(name);
-  return (v && *v) ? std::atoi(v) : dflt;
-}
-
-// The team schedule (xeng_team_kernel) for 5 to 11 row panels of 128 inputs
-// when every XCD gets at least two steps per team: teams of n_full =
-// nb(nb-1)/2 workgroups in the slots the GPU holds at once.
-struct TeamShape {
-  int nb = 0, n_full = 0, teams = 0, grid = 0;
-};
-TeamShape team_shape(const corr_config& c) {
-  TeamShape t;
-  if (env_int("CORR_TEAM", 1) == 0) return t;
-  const TeamHw h = team_hw();
-  if (h.cus <= 0 || h.per_cu <= 0 || h.cus % corr::kNumXcd != 0) return t;
-  const int nb = (c.n_inputs + 127) / 128;
-  const int n_full = nb * (nb - 1) / 2;
-  const int slots = h.per_cu * h.cus / corr::kNumXcd;
-  if (nb < 5 || n_full > slots) return t;
-  const int teams = std::min(3, slots / n_full);
-  if ((int64_t)c.n_channels < 2LL * corr::kNumXcd * teams) return t;
-  t.nb = nb;
-  t.n_full = n_full;
-  t.teams = teams;
-  t.grid = slots * corr::kNumXcd;
-  return t;
-}
-hipError_t launch_team(const corr_config& c, const corr::XArgs& a, int elem, uint32_t* sync, size_t sync_bytes,
-                       hipStream_t st) {
-  const TeamShape ts = team_shape(c);
-  hipError_t e = corr::launch_fill_zero(sync, (int64_t)sync_bytes, st);
-  if (e != hipSuccess) return e;
-  corr::TeamArgs t;
-  std::memset(&t, 0, sizeof(t));
-  t.x = a;
-  t.sync = sync;
-  t.nb = ts.nb;
-  t.n_full = ts.n_full;
-  t.teams = ts.teams;
-  t.slack = env_int("CORR_TEAM_SLACK", 0);
-  t.spin_limit = env_int("CORR_TEAM_SPIN", 400);
-  return corr::launch_xeng_team(t, elem, ts.grid, st);
-}
-
 // Launch one X-engine pass over samples [n_ch][n_in][row_stride] (bytes per
 // sample `sb`), n_samples per row, into the plan's accumulator.
 corr_status xengine_pass(corr_plan* p, const void* x, int sb, int64_t n_samples, int64_t row_stride,
-                         int elem = -1, const float* inv_scale2 = nullptr) {
+                         int elem = -1, const float* inv_scale2 = nullptr, const uint32_t* m_bits = nullptr) {
   const Layout& L = p->L;
   corr_xpass q;
   std::memset(&q, 0, sizeof(q));
@@ -264,12 +195,11 @@ corr_status xengine_pass(corr_plan* p, const void* x, int sb, int64_t n_samples,
   q.row_stride = row_stride;
   q.elem = elem;
   q.inv_scale2 = inv_scale2;
+  q.m_bits = m_bits;
   q.acc = at(p, L.acc);
   q.accumulate = p->acc_zero ? 0 : 1;
   q.part = L.part_bytes ? at(p, L.part) : nullptr;
   q.part_bytes = L.part_bytes;
-  q.sync = L.sync_bytes ? static_cast<uint32_t*>(at(p, L.sync)) : nullptr;
-  q.sync_bytes = L.sync_bytes;
   q.stream = p->stream;
   const corr_status st = corr_internal_xengine(&q);
   if (st == CORR_E_HIP) p->error = true;
@@ -289,8 +219,6 @@ int corr_internal_split(const corr_config* c, int64_t n_samples) {
   return (int)((n_gran + gran_per_split - 1) / gran_per_split);
 }
 
-size_t corr_internal_sync_bytes() { return (size_t)corr::kNumXcd * corr::kTeamSyncStride * sizeof(uint32_t); }
-
 corr_status corr_internal_xengine(const corr_xpass* q) {
   const corr_config& c = *q->cfg;
   const Layout L = layout_of(&c);
@@ -305,7 +233,10 @@ corr_status corr_internal_xengine(const corr_xpass* q) {
   corr::XArgs a;
   std::memset(&a, 0, sizeof(a));
   a.x = q->x;
-  a.row_stride_b = q->row_stride * sb;
+  // converting engines read float32 rows (8 bytes per sample); their K
+  // counts staged bytes (sb per sample)
+  const bool cvt = q->elem == corr::kElemF16Cvt || q->elem == corr::kElemF8Cvt;
+  a.row_stride_b = q->row_stride * (cvt ? 8 : sb);
   a.ch_stride_b = (int64_t)c.n_inputs * a.row_stride_b;
   a.k_bytes = n_samples * sb;
   a.k_split_bytes = gran_per_split * kSplitGranule * sb;
@@ -323,17 +254,16 @@ corr_status corr_internal_xengine(const corr_xpass* q) {
   a.out_split_stride = direct ? 0 : (int64_t)c.n_channels * L.n_products;
   a.accumulate = direct ? q->accumulate : 0;
   a.inv_scale2 = q->inv_scale2;
+  a.m_bits = q->m_bits;
   const bool aligned = (a.row_stride_b % 16 == 0) && ((reinterpret_cast<uintptr_t>(q->x) & 15) == 0);
-  const bool ci4 = q->elem == corr::kElemCI4;
-  if (ci4 && !aligned) return CORR_E_UNSUPPORTED;   // nibble rows must be 16-byte aligned
-  const bool team = c.engine == CORR_X_I8 && (q->elem < 0 || ci4) && aligned && direct && L.bt == 128 && q->sync &&
-                    q->sync_bytes >= corr_internal_sync_bytes() && team_shape(c).grid > 0;
+  if (q->elem == corr::kElemCI4 && !aligned) return CORR_E_UNSUPPORTED;   // nibble rows must be 16-byte aligned
+  // Off-diagonal tiles first within each XCD (see item_decode) when every XCD
+  // gets whole channels and there are off-diagonal tiles.
+  a.order = (split == 1 && c.n_channels % corr::kNumXcd == 0 && L.n_tiles > 1) ? 1 : 0;
 
   hipError_t e;
   const bool is_int = (c.engine == CORR_X_I8);
-  if (team)
-    e = launch_team(c, a, ci4 ? corr::kElemCI4 : corr::kElemI8, q->sync, q->sync_bytes, q->stream);
-  else if (q->elem >= 0)
+  if (q->elem >= 0)
     e = corr::launch_xeng_mfma(a, q->elem, L.bt, q->stream);  // staged FP16 / FP8 rows and CI4 rows are aligned
   else if (c.engine == CORR_X_I8)
     e = aligned ? corr::launch_xeng_mfma(a, corr::kElemI8, L.bt, q->stream)
@@ -546,6 +476,22 @@ corr_status corr_correlate(corr_plan* p, const void* d_samples, int64_t n_sample
       if (c.engine == CORR_X_I8 && !within(c, total, i32)) return CORR_E_OVERFLOW;
       if (c.engine == CORR_X_FP32 && !within(c, total, 16777216.0)) return CORR_E_OVERFLOW;
     }
+    if ((c.engine == CORR_X_F16 || c.engine == CORR_X_F8) && c.ring_samples == 0) {
+      // Convert while staging (one pass over the float32 samples; FP8 first
+      // takes the per-channel maximum of this call's samples).
+      if ((reinterpret_cast<uintptr_t>(x) % 8) != 0) return CORR_E_UNSUPPORTED;
+      const bool f8 = c.engine == CORR_X_F8;
+      if (f8 && n > 0) {
+        const hipError_t e = corr::launch_absmax(static_cast<const float*>(x), c.n_channels, c.n_inputs, n, stride,
+                                                 static_cast<uint32_t*>(at(p, p->L.mbits)), p->stream);
+        if (e != hipSuccess) return hip_fail(p, e);
+      }
+      const corr_status st = xengine_pass(p, x, f8 ? 2 : 4, n, stride, f8 ? corr::kElemF8Cvt : corr::kElemF16Cvt,
+                                          nullptr, f8 ? static_cast<const uint32_t*>(at(p, p->L.mbits)) : nullptr);
+      if (st != CORR_OK) return st;
+      p->n_accum = total;
+      return CORR_OK;
+    }
     if (c.engine == CORR_X_F16 || c.engine == CORR_X_F8) {
       // Stage chunks of at most ring_samples samples, then correlate each.
       const int elem = (c.engine == CORR_X_F16) ? corr::kElemF16 : corr::kElemF8;
@@ -612,6 +558,7 @@ corr_status corr_stage_read(corr_plan* p, void* dst, float* scales, int64_t* n_s
     if (p->error) return CORR_E_STATE;
     const corr_config& c = p->cfg;
     if (c.engine != CORR_X_F16 && c.engine != CORR_X_F8) return CORR_E_STATE;
+    if (c.ring_samples == 0) return CORR_E_STATE;   // converting plan: nothing staged
     const int64_t n = p->stage_fill;
     const int64_t rows = (int64_t)c.n_channels * c.n_inputs;
     const int sb = p->L.stage_sb;
@@ -704,8 +651,11 @@ corr_status corr_dump(corr_plan* p, int32_t what, void* dst, int32_t dst_is_devi
       e = hipMemcpyAsync(dst, at(p, L.longrun), L.longrun_bytes, kind, p->stream);
       if (e != hipSuccess) return hip_fail(p, e);
     }
-    e = hipStreamSynchronize(p->stream);
-    if (e != hipSuccess) return hip_fail(p, e);
+    // A plain reset (no copy, no fold) queues nothing and need not wait.
+    if (integ || longrun || fold) {
+      e = hipStreamSynchronize(p->stream);
+      if (e != hipSuccess) return hip_fail(p, e);
+    }
     if (integ && p->acc_zero && !dst_is_device) std::memset(dst, 0, L.acc_bytes);
     if (n_samples_out) *n_samples_out = p->n_accum;
     if (exact_out) {

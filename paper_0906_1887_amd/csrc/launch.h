@@ -12,16 +12,12 @@ struct FArgs;
 // int8 MFMA X-engine; bt = 64 or 128; aligned: rows and base 16-byte aligned.
 hipError_t launch_xeng_i8(const XArgs& a, int bt, bool aligned, hipStream_t s);
 // Matrix-core X-engine for 16-byte aligned rows; elem = kElemI8 / kElemF16 / kElemF8
-// (bt 64 or 128), or kElemCI4 (bt 128).
+// (bt 64 or 128), or kElemCI4 / kElemF16Cvt / kElemF8Cvt (bt 128).
 hipError_t launch_xeng_mfma(const XArgs& a, int elem, int bt, hipStream_t s);
-// Team-scheduled 128-row int8 engine (persistent grid of `grid` workgroups).
-hipError_t launch_xeng_team(const TeamArgs& t, int elem, int grid, hipStream_t s);
-// Workgroups of the team kernel one CU holds at once (0 if unknown).
-int team_blocks_per_cu();
-// Serving grid over the device job queue (int8, aligned rows).
-// Tiles of bt = 64 or 128 rows: a grid serves only the jobs of its tile size.
-hipError_t launch_xeng_serve(const ServeQueue& q, int bt, int grid, hipStream_t s);
-int serve_blocks_per_cu(int bt);
+// Serving grid over the device job queue (int8, aligned rows, 128-row tiles);
+// grid = workgroups.
+hipError_t launch_xeng_serve(const ServeQueue& q, int grid, hipStream_t s);
+int serve_blocks_per_cu();
 // FP32 X-engine; sample_bytes = 8 (complex float32) or 2 (complex int8).
 hipError_t launch_xeng_f32(const XArgs& a, int sample_bytes, int bt, bool aligned, hipStream_t s);
 hipError_t launch_reduce_splits(const void* part, int64_t n_pairs, int n_split, void* acc, int accumulate,
@@ -64,5 +60,8 @@ struct LowpCall {
   float* inv_scale2;       // FP8: per-channel 1/s_c^2 (output)
 };
 hipError_t launch_lowp_stage(const LowpCall& c, hipStream_t s);
+// Per-channel max |re|, |im| (float bits) of complex float32 [n_ch][n_in][row_stride] rows.
+hipError_t launch_absmax(const float* x, int64_t n_ch, int64_t n_in, int64_t n_t, int64_t row_stride, uint32_t* m_bits,
+                         hipStream_t s);
 
 }  // namespace corr

@@ -57,18 +57,6 @@ __global__ __launch_bounds__(256) void absmax_kernel(const float* __restrict__ x
   if (tid == 0) atomicMax(&m_bits[ch], __float_as_uint(red[0]));
 }
 
-// The exponent is clamped to [-60, 60] (so 1/s^2 stays a normal float) and
-// the correction loops are bounded; within that range the result is exact,
-// because s is a power of two and the comparisons are exact.
-__device__ __forceinline__ float e4m3_scale(float m) {
-  if (!(m > 0.f) || !(m < INFINITY)) return 1.f;
-  const float e = fminf(fmaxf(floorf(log2f(448.f / m)), -60.f), 60.f);
-  float s = ldexpf(1.f, (int)e);
-  for (int k = 0; k < 4 && s * m > 448.f && s > 0x1p-60f; ++k) s *= 0.5f;
-  for (int k = 0; k < 4 && 2.f * s * m <= 448.f && s < 0x1p60f; ++k) s *= 2.f;
-  return s;
-}
-
 // One thread converts 4 complex samples of one row (grid: sample groups x
 // rows x channels).  Out rows have out_stride samples; FP16: 4 bytes per
 // sample, FP8: 2.  VEC: the row starts 16-byte aligned, so full groups are
@@ -129,23 +117,29 @@ __global__ __launch_bounds__(256) void lowp_convert_kernel(const float* __restri
   }
 }
 
+// Per-channel max |re|, |im| of complex float32 rows into m_bits (zeroed first).
+hipError_t launch_absmax(const float* x, int64_t n_ch, int64_t n_in, int64_t n_t, int64_t row_stride, uint32_t* m_bits,
+                         hipStream_t s) {
+  if (n_ch <= 0 || n_in <= 0) return hipSuccess;
+  if (n_ch > 65535) return hipErrorInvalidValue;
+  hipError_t e = launch_fill_zero(m_bits, (n_ch * 4 + 15) / 16 * 16, s);
+  if (e != hipSuccess || n_t <= 0) return e;
+  const bool vec = (reinterpret_cast<uintptr_t>(x) % 16 == 0) && (row_stride % 2 == 0);
+  const int64_t rows_per_wg = 4;
+  const dim3 g((unsigned)((n_in + rows_per_wg - 1) / rows_per_wg), (unsigned)n_ch);
+  if (vec)
+    hipLaunchKernelGGL(absmax_kernel<true>, g, dim3(256), 0, s, x, n_in, n_t, row_stride, rows_per_wg, m_bits);
+  else
+    hipLaunchKernelGGL(absmax_kernel<false>, g, dim3(256), 0, s, x, n_in, n_t, row_stride, rows_per_wg, m_bits);
+  return hipGetLastError();
+}
+
 hipError_t launch_lowp_stage(const LowpCall& c, hipStream_t s) {
   if (c.n_ch <= 0 || c.n_in <= 0 || c.n_t <= 0) return hipSuccess;
   if (c.n_ch > 65535 || c.n_in > 65535) return hipErrorInvalidValue;
   const bool vec = (reinterpret_cast<uintptr_t>(c.x) % 16 == 0) && (c.row_stride % 2 == 0);
-  hipError_t e;
   if (c.elem == kElemF8) {
-    e = launch_fill_zero(c.m_bits, (c.n_ch * 4 + 15) / 16 * 16, s);
-    if (e != hipSuccess) return e;
-    const int64_t rows_per_wg = 4;
-    const dim3 g((unsigned)((c.n_in + rows_per_wg - 1) / rows_per_wg), (unsigned)c.n_ch);
-    if (vec)
-      hipLaunchKernelGGL(absmax_kernel<true>, g, dim3(256), 0, s, c.x, (int64_t)c.n_in, c.n_t, c.row_stride,
-                         rows_per_wg, c.m_bits);
-    else
-      hipLaunchKernelGGL(absmax_kernel<false>, g, dim3(256), 0, s, c.x, (int64_t)c.n_in, c.n_t, c.row_stride,
-                         rows_per_wg, c.m_bits);
-    e = hipGetLastError();
+    const hipError_t e = launch_absmax(c.x, c.n_ch, c.n_in, c.n_t, c.row_stride, c.m_bits, s);
     if (e != hipSuccess) return e;
   }
   const int64_t gx = ((c.n_t + 3) / 4 + 255) / 256;

@@ -10,14 +10,16 @@
 //
 // Device queue (the batched path).  An admitted job is published in a slot
 // of a job queue in the arena's head: its pass (sample and result pointers,
-// shape) and the claim limit of its work items, one per (channel, 128- or
-// 64-row baseline tile).  Persistent serving grids (xeng_serve_kernel, one per
-// tile size) run while published work remains: every workgroup claims items
-// round robin over the listed jobs, so jobs that arrive while others run are
-// taken up by the grid already on the device and a small job is not queued
-// behind a large one; a grid's workgroups exit once the queue is empty, and
-// the scheduler launches a new grid when work is published and none is
-// running.  The workgroup that finishes a job's last item writes the job's
+// shape) and the claim limit of its work items, one per (channel, 128-row
+// baseline tile).  A persistent serving grid (xeng_serve_kernel, as many
+// workgroups as the GPU holds at once) runs while published work remains:
+// every workgroup claims items round robin over the listed jobs, so jobs that
+// arrive while others run are taken up by the grid already on the device and
+// a small job is not queued behind a large one.  Once the queue has been idle
+// for kIdleUs the grid closes as a whole; the scheduler launches a new
+// full-size grid (alternating between two streams, so it can start while the
+// closing one finishes its last tiles) when work is published after the last
+// launch and no open grid is running.  The workgroup that finishes a job's last item writes the job's
 // completion word in pinned host memory.  Results go straight to a device
 // destination; a host destination gets the integration through a copy from
 // the arena (the latency end point is then the landed copy).  There is no
@@ -54,7 +56,8 @@ constexpr int kLookahead = 16;
 constexpr int kSlots = 64;               // jobs on the device queue at once
 constexpr int kStage = 512;              // pinned staging entries for queue updates
 constexpr size_t kStageBytes = 512;
-constexpr int kIdlePolls = 64;           // empty polls before a serving workgroup exits
+constexpr double kIdleUs = 100.0;        // queue idle this long: the serving grid closes
+constexpr int kMaxPolls = 1 << 18;       // bound on one serving workgroup's empty polls
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -74,7 +77,7 @@ struct Job {
   size_t samples_bytes = 0, result_bytes = 0;
   int64_t fill_stride = 0;             // samples between rows of a filled job
   bool queued_path = true;             // device queue, else per-job plan
-  int slot = -1, bt = 128;
+  int slot = -1;
   uint64_t items = 0;
   uint32_t flag_value = 0;
   corr_plan* plan = nullptr;
@@ -150,7 +153,7 @@ corr_config job_config(const corr_job_desc& d) {
 
 // Device-queue layout in the arena's head (byte offsets).
 struct QueueLayout {
-  size_t slots = 0, limit = 0, claim = 0, done = 0, active = 0, rr = 0, total = 0;
+  size_t slots = 0, limit = 0, claim = 0, done = 0, active = 0, rr = 0, last_claim = 0, closing = 0, total = 0;
 };
 QueueLayout queue_layout() {
   QueueLayout q;
@@ -167,6 +170,10 @@ QueueLayout queue_layout() {
   off = align_up(off + (kSlots + 1) * 4);
   q.rr = off;
   off = align_up(off + 128);
+  q.last_claim = off;
+  off = align_up(off + 128);
+  q.closing = off;
+  off = align_up(off + 128);
   q.total = off;
   return q;
 }
@@ -179,15 +186,19 @@ struct corr_sched {
   std::vector<hipStream_t> streams;        // per-job path
   std::vector<int> stream_jobs;            // running per-job-path jobs per stream
   hipStream_t s_ctl = nullptr;             // fills and queue updates
-  hipStream_t s_grid[2] = {nullptr, nullptr};  // serving grids: 128- and 64-row tiles
+  hipStream_t s_grid[2] = {nullptr, nullptr};  // serving grids, alternately
   hipStream_t s_copy = nullptr;            // results to host destinations
   hipEvent_t ev_pub = nullptr;             // after the latest queue update
   hipEvent_t ev_grid[2] = {nullptr, nullptr};
-  bool grid_launched[2] = {false, false};
-  int grid_cap[2] = {0, 0};                // workgroups the GPU holds at once
+  bool grid_alive[2] = {false, false};     // launched, completion not yet seen
+  uint32_t grid_gen[2] = {0, 0};           // generation of the grid on each stream
+  uint32_t next_gen = 0;
+  bool work_since_launch = false;          // a job was published after the latest grid launch
+  int grid_cap = 0;                        // workgroups the GPU holds at once
   QueueLayout ql;
   corr::ServeQueue q{};
-  uint32_t* flags = nullptr;               // pinned host: completion words, one line per slot
+  uint32_t* flags = nullptr;               // pinned host: completion words, one line per slot,
+                                           // then the closed-grid generation
   uint32_t* d_flags = nullptr;             // their device view
   uint8_t* stage = nullptr;                // pinned host staging ring for queue updates
   hipEvent_t stage_ev[kStage] = {};
@@ -251,7 +262,7 @@ hipError_t publish_active(corr_sched* s) {
   int n = 0;
   for (int k = 0; k < kSlots; ++k) {
     const Job* j = s->slot_job[k];
-    if (j && j->state.load() == kRunning) list[1 + n++] = k | (j->bt == 64 ? corr::kServeSmall : 0);
+    if (j && j->state.load() == kRunning) list[1 + n++] = k;
   }
   list[0] = n;
   s->active_dirty = false;
@@ -281,7 +292,7 @@ corr_status launch_queued(corr_sched* s, Job* j) {
   }
   corr::ServeJob sj;
   std::memset(&sj, 0, sizeof(sj));
-  const int64_t nb = (d.n_inputs + j->bt - 1) / j->bt;
+  const int64_t nb = (d.n_inputs + 127) / 128;
   corr::XArgs& a = sj.x;
   a.x = samples;
   a.row_stride_b = stride * 2;
@@ -300,7 +311,6 @@ corr_status launch_queued(corr_sched* s, Job* j) {
   if (j->flag_value == 0) j->flag_value = ++s->next_flag;
   sj.flag = s->d_flags + (size_t)j->slot * corr::kServeLine;
   sj.flag_value = j->flag_value;
-  sj.bt = j->bt;
   sj.base = s->slot_limit[j->slot];
   s->slot_limit[j->slot] += j->items;
   const uint64_t lim = s->slot_limit[j->slot];
@@ -310,6 +320,7 @@ corr_status launch_queued(corr_sched* s, Job* j) {
   hipError_t r = stage_copy(s, s->ql.slots + (size_t)j->slot * sizeof(corr::ServeJob), &sj, sizeof(sj));
   if (r == hipSuccess) r = stage_copy(s, s->ql.limit + (size_t)j->slot * corr::kServeLine * 4, &lim, sizeof(lim));
   if (r == hipSuccess) r = publish_active(s);
+  s->work_since_launch = true;
   return r == hipSuccess ? CORR_OK : CORR_E_HIP;
 }
 
@@ -355,23 +366,30 @@ void launch_plan_job(corr_sched* s, Job* j) {
   }
 }
 
-// Launch a serving grid for each tile size that has published, unfinished
-// work and no grid still running (lock held).
+// Launch a full-size serving grid when a job was published after the latest
+// launch and no open grid is running (lock held).  An open grid takes new work
+// itself; a closing one takes none, so the work waits for the new grid, which
+// may start on the other stream while the closing grid finishes its tiles.
 void launch_grids(corr_sched* s) {
-  uint64_t work[2] = {0, 0};
-  for (int k = 0; k < kSlots; ++k) {
-    const Job* j = s->slot_job[k];
-    if (j && j->state.load() == kRunning) work[j->bt == 128 ? 0 : 1] += j->items;
-  }
+  for (int g = 0; g < 2; ++g)
+    if (s->grid_alive[g] && hipEventQuery(s->ev_grid[g]) != hipErrorNotReady) s->grid_alive[g] = false;
+  if (!s->work_since_launch || s->grid_cap <= 0) return;
+  const uint32_t closed = __atomic_load_n(s->flags + (size_t)kSlots * corr::kServeLine, __ATOMIC_ACQUIRE);
+  int free_g = -1;
   for (int g = 0; g < 2; ++g) {
-    if (!work[g] || s->grid_cap[g] <= 0) continue;
-    if (s->grid_launched[g] && hipEventQuery(s->ev_grid[g]) == hipErrorNotReady) continue;
-    const int grid = (int)std::min<uint64_t>(work[g], (uint64_t)s->grid_cap[g]);
-    if (hipStreamWaitEvent(s->s_grid[g], s->ev_pub, 0) != hipSuccess) continue;
-    if (corr::launch_xeng_serve(s->q, g == 0 ? 128 : 64, grid, s->s_grid[g]) == hipSuccess &&
-        hipEventRecord(s->ev_grid[g], s->s_grid[g]) == hipSuccess)
-      s->grid_launched[g] = true;
+    if (s->grid_alive[g] && s->grid_gen[g] > closed) return;   // an open grid is running
+    if (!s->grid_alive[g] && free_g < 0) free_g = g;
   }
+  if (free_g < 0) return;                                        // both streams hold closing grids
+  corr::ServeQueue q = s->q;
+  q.gen = s->next_gen + 1;
+  if (hipStreamWaitEvent(s->s_grid[free_g], s->ev_pub, 0) != hipSuccess) return;
+  if (corr::launch_xeng_serve(q, s->grid_cap, s->s_grid[free_g]) != hipSuccess) return;
+  if (hipEventRecord(s->ev_grid[free_g], s->s_grid[free_g]) != hipSuccess) return;
+  s->next_gen = q.gen;
+  s->grid_gen[free_g] = q.gen;
+  s->grid_alive[free_g] = true;
+  s->work_since_launch = false;
 }
 
 void retire_job(corr_sched* s, Job* j) {
@@ -467,7 +485,7 @@ void worker_loop(corr_sched* s) {
     if (s->active_dirty) publish_active(s);
     launch_grids(s);
     if (s->stop && s->pending.empty() && s->running.empty()) break;
-    bool busy = false;
+    bool busy = s->work_since_launch || s->grid_alive[0] || s->grid_alive[1];
     for (const Job* j : s->running) busy = busy || (j->queued_path && j->state.load() == kRunning);
     s->cv.wait_for(lk, std::chrono::microseconds(busy ? 20 : 200));
   }
@@ -508,7 +526,7 @@ corr_status corr_sched_create(void* d_arena, size_t arena_bytes, int32_t n_strea
       ok = hipEventCreateWithFlags(&s->stage_ev[k], hipEventDisableTiming) == hipSuccess;
     // Pinned host memory (allocated, not registered): completion words the
     // serving grids write, and the staging ring for queue updates.
-    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&s->flags), kSlots * corr::kServeLine * 4,
+    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&s->flags), (kSlots + 1) * corr::kServeLine * 4,
                              hipHostMallocMapped) == hipSuccess;
     ok = ok && hipHostMalloc(reinterpret_cast<void**>(&s->stage), kStage * kStageBytes, hipHostMallocDefault) ==
                    hipSuccess;
@@ -521,14 +539,14 @@ corr_status corr_sched_create(void* d_arena, size_t arena_bytes, int32_t n_strea
       corr_sched_destroy(s);
       return CORR_E_HIP;
     }
-    std::memset(s->flags, 0, kSlots * corr::kServeLine * 4);
+    std::memset(s->flags, 0, (kSlots + 1) * corr::kServeLine * 4);
     s->d_flags = static_cast<uint32_t*>(d_flags);
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-                                                 hipSuccess)
-      cus = 0;
-    s->grid_cap[0] = corr::serve_blocks_per_cu(128) * cus;
-    s->grid_cap[1] = corr::serve_blocks_per_cu(64) * cus;
+    int dev = 0, cus = 0, clock_khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+      cus = 0;   // no serving grid: every job takes the per-job path
+    s->grid_cap = corr::serve_blocks_per_cu() * cus;
     s->q.slots = reinterpret_cast<const corr::ServeJob*>(s->arena_base + ql.slots);
     s->q.limit = reinterpret_cast<const uint64_t*>(s->arena_base + ql.limit);
     s->q.claim = reinterpret_cast<uint64_t*>(s->arena_base + ql.claim);
@@ -536,7 +554,11 @@ corr_status corr_sched_create(void* d_arena, size_t arena_bytes, int32_t n_strea
     s->q.active = reinterpret_cast<const int32_t*>(s->arena_base + ql.active);
     s->q.rr = reinterpret_cast<uint32_t*>(s->arena_base + ql.rr);
     s->q.n_slots = kSlots;
-    s->q.idle_polls = kIdlePolls;
+    s->q.last_claim = reinterpret_cast<uint64_t*>(s->arena_base + ql.last_claim);
+    s->q.closing = reinterpret_cast<uint32_t*>(s->arena_base + ql.closing);
+    s->q.host_closing = s->d_flags + (size_t)kSlots * corr::kServeLine;
+    s->q.idle_ticks = (uint32_t)std::max(1.0, (double)clock_khz * 1e3 * kIdleUs * 1e-6);
+    s->q.max_polls = kMaxPolls;
     for (int k = kSlots - 1; k >= 0; --k) s->free_slots.push_back(k);
     s->worker = std::thread(worker_loop, s);
     *out = s;
@@ -561,15 +583,14 @@ corr_status corr_sched_submit(corr_sched* s, const corr_job_desc* d, double t_ar
     j->d = *d;
     j->t_arrival = t_arrival;
     j->owner = s;
-    j->bt = d->n_inputs > 64 ? 128 : 64;
-    const int64_t nb = (d->n_inputs + j->bt - 1) / j->bt;
+    const int64_t nb = (d->n_inputs + 127) / 128;
     j->items = (uint64_t)d->n_channels * (uint64_t)(nb * (nb + 1) / 2);
     // Filled rows are padded to a multiple of 8 samples (16 bytes).
     j->fill_stride = (d->n_samples + 7) / 8 * 8;
     const int64_t stride = d->row_stride ? d->row_stride : d->n_samples;
     const bool aligned =
         d->fill || ((reinterpret_cast<uintptr_t>(d->d_samples) % 16) == 0 && (stride * 2) % 16 == 0);
-    j->queued_path = aligned && j->items < (1ull << 31);
+    j->queued_path = aligned && j->items < (1ull << 31) && s->grid_cap > 0;
     j->samples_bytes = d->fill ? align_up((size_t)d->n_channels * d->n_inputs * j->fill_stride * 2) : 0;
     j->result_bytes = (size_t)d->n_channels * (size_t)((int64_t)d->n_inputs * (d->n_inputs + 1) / 2) * 8;
     j->bytes = j->queued_path ? j->samples_bytes + (d->dst_is_device ? 0 : align_up(j->result_bytes))

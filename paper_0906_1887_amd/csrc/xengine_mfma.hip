@@ -605,6 +605,251 @@ __device__ __forceinline__ void mfma_tile_128(const XArgs& a, int8_t* lds, int c
     }
 }
 
+// FP16 / FP8 engine reading complex float32 directly (plans without a
+// staging chunk): the conversion of the staged engines moves into the load.
+// A stage's float32 samples (FP16: 16 per row, 128 bytes; FP8: 32 per row,
+// 256 bytes) are fetched with coalesced 16-byte loads (consecutive lanes read
+// consecutive bytes of a row) into registers, kPF stages ahead; each 16-byte
+// load (two complex samples) is converted in registers (round to nearest
+// even; FP8 after scaling by the channel's power of two s_c, saturating) and
+// written to LDS in the staged engine's swizzled layout (8 bytes for FP16, 4
+// for FP8).  The MFMA stage is that of mfma_tile_128, so the sums are those
+// of the staged engine on the same codes.  Two LDS stage buffers, one
+// barrier per stage, one workgroup per CU (the register prefetch takes the
+// room of a second).  Samples past the pass are zero; rows past N_I are read
+// from a clamped row and never stored.
+constexpr int kPF = 3;   // stages of float32 samples in flight per workgroup
+
+// Two floats -> two binary16 (round to nearest even), the first in the low half.
+__device__ __forceinline__ uint32_t pack_f16x2(float lo, float hi) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)lo) | ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)hi) << 16);
+}
+
+template <int EK, bool DIAG>
+__device__ __forceinline__ void mfma_tile_128_cvt(const XArgs& a, int8_t* lds, int ch, int split, int I, int J) {
+  constexpr int EKM = EK == kElemF16Cvt ? kElemF16 : kElemF8;   // the MFMA stage's element kind
+  constexpr int BT = 128;
+  constexpr int PANEL = BT * kMKC;                // bytes per operand per stage
+  constexpr int STAGE = PANEL * (DIAG ? 1 : 2);
+  constexpr int NOP = DIAG ? 1 : 2;
+  constexpr int SB = EKM == kElemF16 ? 4 : 2;     // staged bytes per complex sample
+  constexpr int SPS = kMKC / SB;                  // samples per row per stage
+  constexpr int NF = SPS / 2;                     // float4 (two samples) per row per stage
+  constexpr int L = BT * NF / 256;                // float4 per thread per operand per stage
+  using Acc = typename MAcc<EKM>::T;
+
+  const float* __restrict__ xc = reinterpret_cast<const float*>(static_cast<const int8_t*>(a.x) + (int64_t)ch * a.ch_stride_b);
+  const int64_t k0 = (int64_t)split * a.k_split_bytes;
+  const int64_t k1 = min(a.k_bytes, k0 + a.k_split_bytes);
+  const int n_st = k1 > k0 ? (int)((k1 - k0 + kMKC - 1) / kMKC) : 0;
+  const int64_t t0 = k0 / SB, t1 = k1 / SB;        // sample range of the pass
+  const int64_t rsf = a.row_stride_b / 4;          // floats between rows (row_stride_b: float32 bytes)
+  // float4 loads when every row starts 16-byte aligned, else float2 loads
+  const bool a16 = ((reinterpret_cast<uintptr_t>(xc) | (uintptr_t)a.row_stride_b) & 15) == 0;
+  float sc = 1.f;
+  if constexpr (EKM == kElemF8) sc = e4m3_scale(__uint_as_float(a.m_bits[ch]));
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // This thread's loads: row q_row[q] (of 128), float4 f = q_f[q] of the
+  // row's stage; LDS byte offset of the converted bytes within a panel.
+  const float* src[2][L];
+  int q_f[L], q_lds[L];
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    const int idx = tid + 256 * q;
+    const int r = idx / NF, f = idx % NF;
+    const int kb = f * 2 * SB;                   // K byte of the float4's first sample
+    q_f[q] = f;
+    q_lds[q] = r * kMKC + 16 * ((kb >> 4) ^ swz(r)) + (kb & 15);
+    src[0][q] = xc + (int64_t)min(I * BT + r, a.n_in - 1) * rsf;
+    src[1][q] = xc + (int64_t)min(J * BT + r, a.n_in - 1) * rsf;
+  }
+  float4 R[kPF][NOP][L];
+  auto gload = [&](auto S, int st) {
+    constexpr int sl = decltype(S)::value;
+    const int64_t tb = t0 + (int64_t)st * SPS;
+#pragma unroll
+    for (int o = 0; o < NOP; ++o)
+#pragma unroll
+      for (int q = 0; q < L; ++q) {
+        const int64_t t = tb + 2 * q_f[q];
+        const float* g = src[o][q] + t * 2;
+        float4 v;
+        if (t + 2 <= t1) {
+          if (a16) {
+            v = *reinterpret_cast<const float4*>(g);
+          } else {
+            const float2 u0 = reinterpret_cast<const float2*>(g)[0];
+            const float2 u1 = reinterpret_cast<const float2*>(g)[1];
+            v = make_float4(u0.x, u0.y, u1.x, u1.y);
+          }
+        } else {
+          v = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (t < t1) {
+            v.x = g[0];
+            v.y = g[1];
+          }
+        }
+        R[sl][o][q] = v;
+      }
+  };
+  auto cvt_store = [&](auto S, int buf) {
+    constexpr int sl = decltype(S)::value;
+    int8_t* base = lds + buf * STAGE;
+#pragma unroll
+    for (int o = 0; o < NOP; ++o)
+#pragma unroll
+      for (int q = 0; q < L; ++q) {
+        const float4 v = R[sl][o][q];
+        int8_t* d = base + o * PANEL + q_lds[q];
+        if constexpr (EKM == kElemF16) {
+          *reinterpret_cast<uint2*>(d) = make_uint2(pack_f16x2(v.x, v.y), pack_f16x2(v.z, v.w));
+        } else {
+          int x = __builtin_amdgcn_cvt_pk_fp8_f32(sc * v.x, sc * v.y, 0, false);
+          x = __builtin_amdgcn_cvt_pk_fp8_f32(sc * v.z, sc * v.w, x, true);
+          *reinterpret_cast<int*>(d) = x;
+        }
+      }
+  };
+
+  Acc vr[2][2], vi[2][2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        vr[m][n][r] = 0;
+        vi[m][n][r] = 0;
+      }
+
+  const int frow = lane & 31;
+  const int g = lane >> 5;
+  auto read = [&](int buf, v4i (&af)[2][2], v4i (&bf)[2][2]) {
+    const int8_t* As = lds + buf * STAGE;
+    const int8_t* Bs = DIAG ? As : As + PANEL;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int cidx = 2 * h + g;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int r = wm * 64 + m * 32 + frow;
+        af[m][h] = *reinterpret_cast<const v4i*>(As + r * kMKC + 16 * (cidx ^ swz(r)));
+      }
+#pragma unroll
+      for (int n = 0; n < 2; ++n) {
+        const int r = wn * 64 + n * 32 + frow;
+        bf[n][h] = *reinterpret_cast<const v4i*>(Bs + r * kMKC + 16 * (cidx ^ swz(r)));
+      }
+    }
+  };
+  const bool idle = DIAG && wm < wn;        // strictly upper quarter of a diagonal tile
+  const bool sk = DIAG && wm == wn;         // diagonal quarter: skip block (0, 1)
+  auto compute = [&](const v4i (&af)[2][2], const v4i (&bf)[2][2]) {
+    v4i ra[2][2];
+    if constexpr (EKM == kElemF8) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+          if (!(sk && m == 0 && n == 1)) mfma64<EKM>(af[m], bf[n], vr[m][n]);
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) ra[m][h] = rotm4<EKM>(af[m][h]);
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+          if (!(sk && m == 0 && n == 1)) mfma64<EKM>(ra[m], bf[n], vi[m][n]);
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int n = 0; n < 2; ++n)
+            if (!(sk && m == 0 && n == 1)) mfma16<EKM>(af[m][h], bf[n][h], vr[m][n]);
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) ra[m][h] = rotm4<EKM>(af[m][h]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int n = 0; n < 2; ++n)
+            if (!(sk && m == 0 && n == 1)) mfma16<EKM>(ra[m][h], bf[n][h], vi[m][n]);
+    }
+  };
+
+  using S0 = std::integral_constant<int, 0>;
+  static_assert(kPF == 3, "the prologue and the unrolled main loop below are written for 3 slots");
+  // prologue: stages 0, 1, 2 in flight (slot p holds stage p)
+  if (0 < n_st) gload(S0{}, 0);
+  if (1 < n_st) gload(std::integral_constant<int, 1>{}, 1);
+  if (2 < n_st) gload(std::integral_constant<int, 2>{}, 2);
+  if (n_st > 0) {
+    cvt_store(S0{}, 0);
+    if (kPF < n_st) gload(S0{}, kPF);
+  }
+  __syncthreads();
+  // Stage st lives in register slot st % kPF; iteration st converts stage
+  // st + 1 (freeing its slot) and refills that slot with stage st + 1 + kPF.
+  auto step = [&](auto U, int st) {
+    constexpr int u = decltype(U)::value;
+    constexpr int nx = (u + 1) % kPF;
+    v4i af[2][2], bf[2][2];
+    if (!idle) read(st & 1, af, bf);
+    if (st + 1 < n_st) {
+      cvt_store(std::integral_constant<int, nx>{}, (st + 1) & 1);   // the buffer last read in stage st - 1
+      if (st + 1 + kPF < n_st) gload(std::integral_constant<int, nx>{}, st + 1 + kPF);
+    }
+    if (!idle) compute(af, bf);
+    __syncthreads();
+  };
+  for (int st0 = 0; st0 < n_st; st0 += kPF) {
+    step(std::integral_constant<int, 0>{}, st0);
+    if (st0 + 1 < n_st) step(std::integral_constant<int, 1>{}, st0 + 1);
+    if (st0 + 2 < n_st) step(std::integral_constant<int, 2>{}, st0 + 2);
+  }
+  if (idle) return;
+
+  // Epilogue (32 x 32 accumulator layout: register r of lane l holds row
+  // 8*(r/4) + 4*(l/32) + r%4, column l%32).  FP8 sums are s_c^2 V exactly.
+  const float scale = EKM == kElemF8 ? 1.f / (sc * sc) : 1.f;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      if (sk && m == 0 && n == 1) continue;
+      const int j = J * BT + wn * 64 + n * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = I * BT + wm * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (i < a.n_in && j <= i) {
+          const int64_t off = (int64_t)split * a.out_split_stride + (int64_t)ch * a.n_products + tri_index(i, j);
+          float2* pp = static_cast<float2*>(a.out) + off;
+          const float re = vr[m][n][r] * scale;
+          const float im = (i == j) ? 0.f : vi[m][n][r] * scale;
+          if (a.accumulate) {
+            float2 o = *pp;
+            o.x += re;
+            o.y += im;
+            *pp = o;
+          } else {
+            *pp = make_float2(re, im);
+          }
+        }
+      }
+    }
+}
+
 // CI4 samples (one byte per complex sample: re in bits 7..4, im in bits 3..0,
 // two's complement nibbles, the "1-byte" mode of Sec. 5) are unpacked in
 // registers into int8 operands scaled by 16: the byte's high nibble with the
@@ -921,12 +1166,8 @@ __global__ __launch_bounds__(256, 2) void xeng_mfma_128_kernel(XArgs a) {
   const int64_t slot = blockIdx.x / kNumXcd;
   const int64_t item = xcd_item(blockIdx.x, a.per_xcd);
   if (slot >= a.per_xcd || item >= a.n_items) return;
-  const int tile = (int)(item % a.n_tiles);
-  const int64_t rest = item / a.n_tiles;
-  const int split = (int)(rest % a.n_split);
-  const int ch = (int)(rest / a.n_split);
-  int I, J;
-  tile_decode(tile, I, J);
+  int ch, split, I, J;
+  item_decode(a, item, ch, split, I, J);
   if constexpr (EK == kElemI8 || EK == kElemCI4) {
     if (I == J) mfma_tile_128_i8<EK, true>(a, lds, ch, split, I, J);
     else mfma_tile_128_i8<EK, false>(a, lds, ch, split, I, J);
@@ -936,79 +1177,16 @@ __global__ __launch_bounds__(256, 2) void xeng_mfma_128_kernel(XArgs a) {
   }
 }
 
-// Team schedule of the 128-row int8 engine for arrays of 5 to 11 row panels
-// (N_I from 513 to 1408).  A persistent grid of exactly the workgroups the GPU
-// holds at once; the slots of each XCD form teams of n_full workgroups, one
-// per off-diagonal tile of a channel, and a team works through the XCD's
-// channels one step (channel) at a time.  Every member of a team runs the same
-// amount of work (a full 128 x 128 tile over all samples) and starts a step
-// when the whole team has finished the step before (give or take `slack`
-// steps), so the eight or so tiles that read each 64-byte piece of a row panel
-// fetch it within a short window and the XCD's L2 serves all but the first.
-// Diagonal tiles (half the loads, 9/16 of the matrix work) would break that
-// rhythm; they form a per-XCD queue drained by the spare slots and, at the
-// end, by the team members.  The waits are bounded (spin_limit polls): they
-// only shape the timing and never decide a result, so a member that gives up
-// waiting still computes its tile exactly.
 template <int EK>
-__global__ __launch_bounds__(256, 2) void xeng_team_kernel(TeamArgs t) {
-  __shared__ __attribute__((aligned(1024))) int8_t lds[kMNS * 2 * 128 * kMKC];
-  __shared__ int next_item;
-  const XArgs& a = t.x;
-  const int xcd = (int)(blockIdx.x % kNumXcd);
-  const int slot = (int)(blockIdx.x / kNumXcd);
-  const int c0 = (int)(((int64_t)xcd * a.n_ch) / kNumXcd);
-  const int c1 = (int)(((int64_t)(xcd + 1) * a.n_ch) / kNumXcd);
-  uint32_t* sync = t.sync + xcd * kTeamSyncStride;
-  if (slot < t.teams * t.n_full) {
-    const int team = slot / t.n_full;
-    const int member = slot % t.n_full;
-    int I, J;
-    tile_decode(member, I, J);      // strictly lower tile m = I(I-1)/2 + J
-    I += 1;
-    uint32_t* ctr = sync + kTeamSyncLine * team;
-    for (int k = 0;; ++k) {
-      const int ch = c0 + k * t.teams + team;
-      if (ch >= c1) break;
-      if (threadIdx.x == 0 && k > t.slack) {
-        const uint32_t target = (uint32_t)(t.n_full * (k - t.slack));
-        for (int w = 0; w < t.spin_limit; ++w) {
-          if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
-          __builtin_amdgcn_s_sleep(4);
-        }
-      }
-      __syncthreads();              // also: the previous tile's LDS reads are done
-      mfma_tile_128_i8<EK, false>(a, lds, ch, 0, I, J);
-      if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-  // Diagonal tiles of this XCD's channels, channel-major.
-  const int n_diag = (c1 - c0) * t.nb;
-  uint32_t* q = sync + kTeamSyncLine * t.teams;
-  for (;;) {
-    __syncthreads();                // previous tile's LDS reads done; next_item free
-    if (threadIdx.x == 0)
-      next_item = (int)__hip_atomic_fetch_add(q, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const int idx = next_item;
-    if (idx >= n_diag) break;
-    const int ch = c0 + idx / t.nb;
-    const int I = idx % t.nb;
-    mfma_tile_128_i8<EK, true>(a, lds, ch, 0, I, I);
-  }
-}
-
-hipError_t launch_xeng_team(const TeamArgs& t, int elem, int grid, hipStream_t s) {
-  if (elem == kElemCI4) hipLaunchKernelGGL(xeng_team_kernel<kElemCI4>, dim3((unsigned)grid), dim3(256), 0, s, t);
-  else hipLaunchKernelGGL(xeng_team_kernel<kElemI8>, dim3((unsigned)grid), dim3(256), 0, s, t);
-  return hipGetLastError();
-}
-
-int team_blocks_per_cu() {
-  int n = 0, m = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, xeng_team_kernel<kElemI8>, 256, 0) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, xeng_team_kernel<kElemCI4>, 256, 0) != hipSuccess) return 0;
-  return n < m ? n : m;
+__global__ __launch_bounds__(256, 1) void xeng_cvt_128_kernel(XArgs a) {
+  __shared__ __attribute__((aligned(1024))) int8_t lds[2 * 2 * 128 * kMKC];
+  const int64_t slot = blockIdx.x / kNumXcd;
+  const int64_t item = xcd_item(blockIdx.x, a.per_xcd);
+  if (slot >= a.per_xcd || item >= a.n_items) return;
+  int ch, split, I, J;
+  item_decode(a, item, ch, split, I, J);
+  if (I == J) mfma_tile_128_cvt<EK, true>(a, lds, ch, split, I, J);
+  else mfma_tile_128_cvt<EK, false>(a, lds, ch, split, I, J);
 }
 
 // Diagonal or off-diagonal tile of the BT-row engine (one instantiation site
@@ -1025,94 +1203,121 @@ __global__ __launch_bounds__(256, 2) void xeng_mfma_kernel(XArgs a) {
   const int64_t slot = blockIdx.x / kNumXcd;
   const int64_t item = xcd_item(blockIdx.x, a.per_xcd);
   if (slot >= a.per_xcd || item >= a.n_items) return;
-  const int tile = (int)(item % a.n_tiles);
-  const int64_t rest = item / a.n_tiles;
-  const int split = (int)(rest % a.n_split);
-  const int ch = (int)(rest / a.n_split);
-  int I, J;
-  tile_decode(tile, I, J);
+  int ch, split, I, J;
+  item_decode(a, item, ch, split, I, J);
   mfma_tile_any<EK, BT>(a, lds, ch, split, I, J);
 }
 
 // Serving: a device queue of integration jobs shared by persistent grids.
 // The host scheduler publishes each admitted job in a slot (its sample and
 // output pointers and shape) and lists the active slots; every workgroup of
-// every running serving grid claims work items -- (channel, tile) pairs of
-// some job -- from the listed jobs in turn (round robin over the jobs, so a
-// small job is not queued behind a large one), runs the tile over all of the
-// job's samples, and counts it done.  The workgroup that finishes a job's
-// last item writes the job's completion word in host memory.  A workgroup
-// that finds no work for idle_polls polls exits, so a grid ends soon after
-// the queue drains.
+// the running serving grid claims work items -- (channel, 128-row tile)
+// pairs of some job -- from the listed jobs in turn (round robin over the
+// jobs, so a small job is not queued behind a large one), runs the tile over
+// all of the job's samples, and counts it done.  The workgroup that finishes a
+// job's last item writes the job's completion word in host memory.
+//
+// A grid ends as a whole: once no workgroup has claimed an item for
+// idle_ticks of the 100 MHz wall clock, the first workgroup to notice closes
+// the grid (it raises `closing` to the grid's generation and tells the host),
+// and from then on no workgroup of that generation claims again; each exits
+// after its current tile.  So a running grid never thins out to a few
+// workgroups that would then carry new work alone; work published after the
+// close waits for the next grid, which the scheduler launches at full size.
 __device__ __forceinline__ uint64_t sys_load64(const void* p) {
   return __hip_atomic_load(static_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-template <int BT>
-__global__ __launch_bounds__(256, 2) void xeng_serve_kernel(ServeQueue q) {
-  __shared__ __attribute__((aligned(1024))) int8_t lds[kMNS * 2 * BT * kMKC];
-  __shared__ ServeJob job;
-  __shared__ int s_slot, s_item;
-  for (;;) {
-    __syncthreads();   // the previous tile's LDS reads and `job` uses are done
-    if (threadIdx.x == 0) {
-      int slot = -1;
-      uint64_t claimed = 0;
-      for (int idle = 0; slot < 0 && idle < q.idle_polls; ++idle) {
-        const int n = __hip_atomic_load(q.active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        if (n > 0 && n <= q.n_slots) {
-          const uint32_t r = __hip_atomic_fetch_add(q.rr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          for (int a = 0; a < n && slot < 0; ++a) {
-            const int e = __hip_atomic_load(q.active + 1 + (int)((r + (uint32_t)a) % (uint32_t)n), __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_SYSTEM);
-            if (((e & kServeSmall) != 0) != (BT == 64)) continue;   // the other tile size's job
-            const int s = e & (kServeSmall - 1);
-            if (s >= q.n_slots) continue;
-            uint64_t* cw = q.claim + (size_t)s * (kServeLine / 2);
-            const uint64_t lim = sys_load64(q.limit + (size_t)s * (kServeLine / 2));
-            uint64_t w = __hip_atomic_load(cw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            while (w < lim) {
-              if (__hip_atomic_compare_exchange_strong(cw, &w, w + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT)) {
-                slot = s;
-                claimed = w;
-                break;
-              }
-            }
+// Thread 0: claim one item, or return -1 when the grid has closed (or this
+// workgroup has polled max_polls times without work).
+__device__ int serve_claim(const ServeQueue& q, uint64_t* claimed) {
+  for (int poll = 0; poll < q.max_polls; ++poll) {
+    if (__hip_atomic_load(q.closing, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= q.gen) return -1;
+    const int n = __hip_atomic_load(q.active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (n > 0 && n <= q.n_slots) {
+      const uint32_t r = __hip_atomic_fetch_add(q.rr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int a = 0; a < n; ++a) {
+        const int s = __hip_atomic_load(q.active + 1 + (int)((r + (uint32_t)a) % (uint32_t)n), __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_SYSTEM);
+        if (s < 0 || s >= q.n_slots) continue;
+        uint64_t* cw = q.claim + (size_t)s * (kServeLine / 2);
+        const uint64_t lim = sys_load64(q.limit + (size_t)s * (kServeLine / 2));
+        uint64_t w = __hip_atomic_load(cw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (w < lim) {
+          if (__hip_atomic_compare_exchange_strong(cw, &w, w + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT)) {
+            __hip_atomic_fetch_max(q.last_claim, (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            *claimed = w;
+            return s;
           }
         }
-        if (slot < 0) __builtin_amdgcn_s_sleep(8);
       }
+    }
+    const uint64_t last = __hip_atomic_load(q.last_claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint64_t)wall_clock64() > last + q.idle_ticks) {
+      uint32_t c = __hip_atomic_load(q.closing, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      while (c < q.gen && !__hip_atomic_compare_exchange_strong(q.closing, &c, q.gen, __ATOMIC_RELAXED,
+                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      }
+      if (c < q.gen) __hip_atomic_store(q.host_closing, q.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      return -1;
+    }
+    __builtin_amdgcn_s_sleep(8);
+  }
+  return -1;
+}
+
+// The job's arguments and the claimed item pass through the start of the
+// tile's LDS buffer (one LDS object per kernel: a second one makes the
+// compiler wait for every LDS-bound global load before each LDS read).
+struct ServeClaim {
+  ServeJob job;
+  int32_t slot, item;
+};
+
+__global__ __launch_bounds__(256, 2) void xeng_serve_kernel(ServeQueue q) {
+  __shared__ __attribute__((aligned(1024))) int8_t lds[kMNS * 2 * 128 * kMKC];
+  static_assert(sizeof(ServeClaim) <= sizeof(lds), "claim record fits in the tile buffer");
+  ServeClaim* sc = reinterpret_cast<ServeClaim*>(lds);
+  if (threadIdx.x == 0)   // a new grid counts as activity: it lingers idle_ticks before it may close
+    __hip_atomic_fetch_max(q.last_claim, (uint64_t)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    __syncthreads();   // the previous tile's LDS reads are done
+    if (threadIdx.x == 0) {
+      uint64_t claimed = 0;
+      const int slot = serve_claim(q, &claimed);
       if (slot >= 0) {
         const uint64_t* src = reinterpret_cast<const uint64_t*>(q.slots + slot);
-        uint64_t* dst = reinterpret_cast<uint64_t*>(&job);
+        uint64_t* dst = reinterpret_cast<uint64_t*>(&sc->job);
         for (int k = 0; k < (int)(sizeof(ServeJob) / 8); ++k) dst[k] = sys_load64(src + k);
+        sc->item = (int)(claimed - sc->job.base);
       }
-      s_slot = slot;
-      s_item = slot >= 0 ? (int)(claimed - job.base) : 0;
+      sc->slot = slot;
     }
     __syncthreads();
-    const int slot = s_slot;
+    const int slot = sc->slot;
     if (slot < 0) return;
-    const XArgs a = job.x;
-    const int tile = s_item % a.n_tiles;
-    const int ch = s_item / a.n_tiles;
+    const XArgs a = sc->job.x;
+    const int item = sc->item;
+    uint32_t* const flag_word = sc->job.flag;
+    const uint32_t flag_value = sc->job.flag_value;
+    const uint64_t job_end = sc->job.base + (uint64_t)a.n_items;
+    __syncthreads();   // everyone holds the claim before the tile reuses the buffer
+    const int tile = item % a.n_tiles;
+    const int ch = item / a.n_tiles;
     int I, J;
     tile_decode(tile, I, J);
-    if constexpr (BT == 128) {
-      if (I == J) mfma_tile_128_i8<kElemI8, true>(a, lds, ch, 0, I, J);
-      else mfma_tile_128_i8<kElemI8, false>(a, lds, ch, 0, I, J);
-    } else {
-      mfma_tile_any<kElemI8, BT>(a, lds, ch, 0, I, J);
-    }
+    if (I == J) mfma_tile_128_i8<kElemI8, true>(a, lds, ch, 0, I, J);
+    else mfma_tile_128_i8<kElemI8, false>(a, lds, ch, 0, I, J);
     __threadfence();   // this thread's part of the tile is visible device-wide
     __syncthreads();
     if (threadIdx.x == 0) {
       const uint32_t old = __hip_atomic_fetch_add(q.done + (size_t)slot * kServeLine, 1u, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
-      if ((uint64_t)old + 1 == job.base + (uint64_t)a.n_items) {
+      if ((uint64_t)old + 1 == job_end) {
         __threadfence_system();
-        __hip_atomic_store(job.flag, job.flag_value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(flag_word, flag_value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
       }
     }
   }
@@ -1128,6 +1333,10 @@ hipError_t launch_xeng_mfma(const XArgs& a, int elem, int bt, hipStream_t s) {
     if (bt == 128) CORR_LAUNCH_W2(kElemI8); else CORR_LAUNCH(kElemI8, 64);
   } else if (elem == kElemCI4) {
     CORR_LAUNCH_W2(kElemCI4);   // 128-row tiles only
+  } else if (elem == kElemF16Cvt) {
+    hipLaunchKernelGGL((xeng_cvt_128_kernel<kElemF16Cvt>), g, b, 0, s, a);   // 128-row tiles only
+  } else if (elem == kElemF8Cvt) {
+    hipLaunchKernelGGL((xeng_cvt_128_kernel<kElemF8Cvt>), g, b, 0, s, a);
   } else if (elem == kElemF16) {
     if (bt == 128) CORR_LAUNCH_W2(kElemF16); else CORR_LAUNCH(kElemF16, 64);
   } else {
@@ -1138,19 +1347,15 @@ hipError_t launch_xeng_mfma(const XArgs& a, int elem, int bt, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_xeng_serve(const ServeQueue& q, int bt, int grid, hipStream_t s) {
+hipError_t launch_xeng_serve(const ServeQueue& q, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  if (bt == 128) hipLaunchKernelGGL(xeng_serve_kernel<128>, dim3((unsigned)grid), dim3(256), 0, s, q);
-  else hipLaunchKernelGGL(xeng_serve_kernel<64>, dim3((unsigned)grid), dim3(256), 0, s, q);
+  hipLaunchKernelGGL(xeng_serve_kernel, dim3((unsigned)grid), dim3(256), 0, s, q);
   return hipGetLastError();
 }
 
-int serve_blocks_per_cu(int bt) {
+int serve_blocks_per_cu() {
   int n = 0;
-  const hipError_t e = bt == 128
-                           ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, xeng_serve_kernel<128>, 256, 0)
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, xeng_serve_kernel<64>, 256, 0);
-  return e == hipSuccess ? n : 0;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, xeng_serve_kernel, 256, 0) == hipSuccess ? n : 0;
 }
 
 }  // namespace corr

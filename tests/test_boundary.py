@@ -55,12 +55,16 @@ def test_workspace_and_validation():
         dict(n_inputs=4, n_channels=128, fft_size=256, requant_scale=0.1, ring_samples=0),
         dict(n_inputs=4, n_channels=4, engine="f16", sample_type="ci8", max_abs=0, ring_samples=64),
         dict(n_inputs=4, n_channels=4, engine="f8", sample_type="cf32", max_abs=7, ring_samples=64),
-        dict(n_inputs=4, n_channels=4, engine="f8", sample_type="cf32", max_abs=0, ring_samples=0),
+        dict(n_inputs=4, n_channels=4, engine="f8", sample_type="cf32", max_abs=0, ring_samples=-1),
     ]
     for kw in bad:
         with pytest.raises(_lib.CorrError) as e:
             _lib.corr_workspace_bytes(_cfg(**kw))
         assert e.value.status == _lib.CORR_E_INVAL, kw
+    # converting FP16 / FP8 plans (ring_samples 0) hold no staging buffer
+    conv = _lib.corr_workspace_bytes(_cfg(n_inputs=256, n_channels=1024, engine="f8", sample_type="cf32",
+                                          max_abs=0, ring_samples=0))
+    assert conv == lowp - 1024 * 256 * 4096 * 2
     for kw in (dict(n_inputs=4, n_channels=64, fft_size=128, requant_scale=0.1, ring_samples=10),):
         with pytest.raises(_lib.CorrError) as e:
             _lib.corr_workspace_bytes(_cfg(**kw))

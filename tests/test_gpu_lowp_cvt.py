@@ -1,0 +1,123 @@
+"""GPU parity of the converting FP16 / FP8 X-engines (plans with ring_samples
+0: no staging buffer, the float32 samples are converted as the X-engine loads
+them), through the C ABI.
+
+The conversion is the staged engine's (round to nearest even; FP8 after the
+per-channel power-of-two scale of the call's samples) and the matrix-core
+stage is the same, so on every case the converting plan's dump must equal a
+staged plan's dump bit for bit when the staged plan's chunk holds the whole
+call.  Its kernel-only error against the FP64 oracle on the oracle's own
+encoding of the samples is also checked: FP16 to 5e-7 (the staged engine's
+largest per-case bound, 3.1e-7, rounded up), FP8 to 1e-3 (the FP8 matrix
+core drops the bits of a product more than about 2^-13 below the largest
+product of its group of 8 K elements, so a sum loses at most 8 * 2^-13 of
+its magnitude).
+Cases: input counts around the 128-row tiles, ragged sample counts, rows
+inside wider buffers (16-byte and only 8-byte aligned rows), K-split passes
+with the fused fix-up, accumulation over calls, and the refusal of rows that
+are not 8-byte aligned."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_0906_1887_amd import CORR_DUMP_INTEG, CorrError, Correlator, _lib
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL = {"f16": 5e-7, "f8": 1e-3}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_fro(V, W):
+    num = np.sqrt(np.sum((V - W) ** 2, axis=(1, 2)))
+    den = np.sqrt(np.sum(W ** 2, axis=(1, 2)))
+    return num / den
+
+
+def encoded(x, engine):
+    """Oracle encoding of float32 samples, decoded back to FP64 (the values the
+    matrix core multiplies, divided by the FP8 scale)."""
+    if engine == "f16":
+        return oracle.f16_decode(oracle.f16_encode(x.astype(np.float64)))
+    out = np.empty(x.shape, np.float64)
+    for c in range(x.shape[0]):
+        s = oracle.e4m3_scale(x[c].astype(np.float64))
+        out[c] = oracle.e4m3_decode(oracle.e4m3_encode(x[c].astype(np.float64) * s)) / s
+    return out
+
+
+def dump_of(engine, buf, n_in, n_ch, T, stride, ring, calls=None):
+    c = Correlator(n_in, n_ch, engine=engine, sample_type="cf32", max_abs=0, ring_samples=ring, device=DEV)
+    for t0, t1 in (calls or [(0, T)]):
+        c.correlate_ptr(buf.data_ptr() + 8 * t0, t1 - t0, stride)
+    out, n, exact = c.dump(CORR_DUMP_INTEG, device_out=True)
+    c.close()
+    assert n == T and not exact
+    return out
+
+
+@pytest.mark.parametrize("engine", ["f16", "f8"])
+def test_converting_equals_staged_on_edge_shapes(engine):
+    cases = [(1, 1, 16), (5, 3, 7), (17, 2, 65), (64, 2, 100), (127, 1, 33), (128, 2, 64),
+             (129, 3, 300), (200, 1, 1), (260, 2, 250)]
+    for n_in, n_ch, T in cases:
+        for pad in (0, 5, 6):                     # odd and even strides: 8- or 16-byte aligned rows
+            stride = T + pad
+            say(f"[{engine} cvt] n_in={n_in} n_ch={n_ch} T={T} stride={stride}")
+            x = np.zeros((n_ch, n_in, stride, 2), np.float32)
+            x[:, :, :T] = np.stack([synth.complex_float(8, ch, n_in, T) for ch in range(n_ch)])
+            x[:, :, T:] = 1e30                    # past the call: must not be read into the sums
+            buf = torch.from_numpy(x).to(DEV)
+            got = dump_of(engine, buf, n_in, n_ch, T, stride, 0)
+            want = dump_of(engine, buf, n_in, n_ch, T, stride, max(T, 1))
+            assert torch.equal(got, want), (engine, n_in, n_ch, T, stride)
+            V = got.cpu().numpy().astype(np.float64)
+            W = oracle.xengine_cf64(encoded(x[:, :, :T], engine))
+            err = rel_fro(V, W)
+            assert err.max() < TOL[engine], (engine, n_in, T, err.max())
+            d = oracle.baseline_index(np.arange(n_in), np.arange(n_in))
+            assert np.all(V[:, d, 1] == 0.0)
+
+
+@pytest.mark.parametrize("engine", ["f16", "f8"])
+def test_converting_split_passes_and_accumulation(engine):
+    """64 inputs x 128 channels x 1000 samples: a K-split pass (8 splits, the
+    last split of each tile adds the partials); then the same samples in two
+    calls into one integration, against the staged plan fed the same two calls
+    (FP8: each call takes the scale of its own samples)."""
+    n_in, n_ch, T = 64, 128, 1000
+    x = np.stack([synth.complex_float(9, ch, n_in, T) for ch in range(n_ch)])
+    buf = torch.from_numpy(x).to(DEV)
+    say(f"[{engine} cvt split] one call")
+    got = dump_of(engine, buf, n_in, n_ch, T, T, 0)
+    assert torch.equal(got, dump_of(engine, buf, n_in, n_ch, T, T, T))
+    sample = [0, 77, 127]
+    W = oracle.xengine_cf64(encoded(x[sample], engine))
+    err = rel_fro(got[sample].cpu().numpy().astype(np.float64), W)
+    assert err.max() < TOL[engine], err.max()
+    say(f"[{engine} cvt split] two calls")
+    calls = [(0, 448), (448, T)]
+    got = dump_of(engine, buf, n_in, n_ch, T, T, 0, calls)
+    assert torch.equal(got, dump_of(engine, buf, n_in, n_ch, T, T, 552, calls))
+
+
+def test_converting_refusals():
+    n_in, n_ch, T = 8, 2, 64
+    buf = torch.zeros((n_ch, n_in, T + 1, 2), dtype=torch.float32, device=DEV)
+    for engine in ("f16", "f8"):
+        c = Correlator(n_in, n_ch, engine=engine, sample_type="cf32", max_abs=0, ring_samples=0, device=DEV)
+        with pytest.raises(CorrError) as e:
+            c.correlate_ptr(buf.data_ptr() + 4, T, T + 1)         # rows not 8-byte aligned
+        assert e.value.status == _lib.CORR_E_UNSUPPORTED
+        with pytest.raises(CorrError) as e:
+            c.stage_read()                                          # nothing is staged
+        assert e.value.status == _lib.CORR_E_STATE
+        c.close()

@@ -1,9 +1,11 @@
 """Serving scheduler on the GPU through the C ABI: each job's result is the
 same alone and inside a concurrent mix (bit-exact, integer data), matches the
 oracle, and admission by HBM footprint queues jobs that do not fit.  Jobs
-with 16-byte aligned rows run on the device job queue (persistent grids, no
-per-job plan or launch); results land in device or pinned host buffers;
-caller buffers with an odd row stride take the per-job plan path."""
+with 16-byte aligned rows run on the device job queue (a persistent grid, no
+per-job plan or launch; the grid closes when the queue idles and the
+scheduler launches a new one for later work); results land in device or
+pinned host buffers; caller buffers with an odd row stride take the per-job
+plan path."""
 import sys
 import time
 
@@ -158,7 +160,7 @@ def test_caller_ring_with_row_stride():
 
 def test_queue_host_and_device_destinations_alone_equals_mix():
     """The device job queue with results copied to pinned host memory and
-    written straight to device memory, jobs of both tile sizes submitted
+    written straight to device memory, large and small jobs submitted
     together (a large job first, small ones behind it): every result equals
     the same job run alone, and the oracle; the device-complete time precedes
     the host landing."""
@@ -198,6 +200,39 @@ def test_queue_host_and_device_destinations_alone_equals_mix():
         assert np.array_equal(alone[k], mix[k]), k
         x = synth.ci8(BASE_SEED + ids_m[k], n_ch, n_in, T)
         assert np.array_equal(mix[k].astype(np.int64), oracle.xengine_ci8(x)), k
+
+
+def test_grid_closes_and_new_work_gets_a_new_grid():
+    """Jobs separated by idle gaps longer than the grid's idle close (0.1 ms):
+    each is run by a freshly launched grid; then a burst behind a small first
+    job (the first grid must not stay sized for it: every grid is launched at
+    full size).  Every result equals the oracle."""
+    gen = synth.DeviceGen()
+    fn, user, keep = gen.job_fill(BASE_SEED)
+    s = Scheduler(2 << 30, 2)
+    jobs = [(16, 8, 200), (130, 5, 300), (17, 3, 64)] + [(16, 4, 100)] + [(300, 16, 500)] * 3 + [(64, 32, 777)] * 4
+    outs, ids = [], []
+    try:
+        for k, (n_in, n_ch, T) in enumerate(jobs):
+            out = result_buf(n_in, n_ch)
+            ids.append(s.submit(n_in, n_ch, T, out, fill=fn, fill_user=user))
+            outs.append(out)
+            if k < 3:
+                st, n, ta, td, tv = wait(s, ids[-1])
+                assert st == 0 and n == T
+                time.sleep(0.005)
+        for jid, (n_in, n_ch, T) in zip(ids[3:], jobs[3:]):
+            st, n, ta, td, tv = wait(s, jid)
+            assert st == 0 and n == T
+        stats = s.stats()
+    finally:
+        s.close()
+    del keep
+    assert stats["completed"] == len(jobs) and stats["failed"] == 0
+    for k, (n_in, n_ch, T) in enumerate(jobs):
+        x = synth.ci8(BASE_SEED + ids[k], n_ch, n_in, T)
+        assert np.array_equal(outs[k].cpu().numpy().astype(np.int64), oracle.xengine_ci8(x)), k
+    say("[serving] grid close and relaunch done")
 
 
 def test_odd_row_stride_takes_the_plan_path():
