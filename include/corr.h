@@ -257,6 +257,36 @@ corr_status corr_seq_reset(corr_plan *plan);
 corr_status corr_correlate(corr_plan *plan, const void *d_samples, int64_t n_samples,
                            int64_t row_stride);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * X-engine pass of corr_correlate without a plan or workspace.  cfg: an
+ * X-only configuration (fft_size 0, no long-run accumulator) of the int8
+ * (CORR_X_I8) or plain FP32 engine; CORR_E_UNSUPPORTED for the FP16/FP8
+ * engines.  d_samples: as for corr_correlate ([n_channels][n_inputs]
+ * [row_stride], row_stride 0 = n_samples).  d_out: the caller's device
+ * accumulator [n_channels][P][2] (int32 for CORR_X_I8, float32 for
+ * CORR_X_FP32): the pass is stored into it (accumulate == 0) or added to it
+ * (accumulate != 0; the caller then keeps the total sample count within the
+ * overflow bound, which is checked here for n_samples only).  The same
+ * kernels as corr_correlate give bit-identical results.  Its K-split partial
+ * tiles (written by the pass, then added in split order into d_out by a
+ * reduction kernel) live in a fixed device array of
+ * CORR_STATIC_SCRATCH_BYTES (64 MiB) inside the library, one per GPU, held
+ * until the process ends; its address is looked up on the first call on each
+ * device, which must be the current device and the stream's.  No device
+ * memory is allocated or freed, and nothing in the array needs clearing
+ * between calls.  CORR_E_WORKSPACE if the request needs more than that
+ * array (K-split partials of split * n_channels * P * 8 bytes, for small
+ * arrays with few channels); CORR_E_INVAL / CORR_E_OVERFLOW /
+ * CORR_E_UNSUPPORTED as for corr_correlate; CORR_E_HIP if the address lookup
+ * or a launch fails.
+ * Asynchronous on hip_stream (NULL = default stream).  Every call on a GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (other
+ * streams, other threads) race and must be serialised by the caller. */
+#define CORR_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+corr_status corr_correlate_static(const corr_config *cfg, const void *d_samples, int64_t n_samples,
+                                  int64_t row_stride, void *d_out, int32_t accumulate, void *hip_stream);
+
 /* corr_dump `what` flags. */
 #define CORR_DUMP_INTEG    1  /* copy the integration accumulator to dst      */
 #define CORR_DUMP_LONGRUN  2  /* copy the FP64 long-run accumulator to dst    */

@@ -37,7 +37,7 @@ EXPORTED = [
     "corr_workspace_bytes", "corr_create", "corr_destroy", "corr_channelise", "corr_seq_reset",
     "corr_correlate", "corr_dump", "corr_ring_read", "corr_stage_read", "corr_dump_bytes", "corr_status_str",
     "corr_sched_now", "corr_sched_create", "corr_sched_submit", "corr_sched_poll", "corr_sched_stats",
-    "corr_sched_destroy", "corr_aggregate_w16", "corr_cmac_design",
+    "corr_sched_destroy", "corr_aggregate_w16", "corr_cmac_design", "corr_correlate_static",
 ]
 
 
@@ -101,6 +101,7 @@ def lib():
         L.corr_aggregate_w16.argtypes = [P, I32, I32, I64, ctypes.c_uint32, P, P, P]
         L.corr_cmac_design.argtypes = [I32, I32, P, I64, I32, I32, P, I32, P]
         L.corr_correlate.argtypes = [P, P, I64, I64]
+        L.corr_correlate_static.argtypes = [ctypes.POINTER(corr_config), P, I64, I64, P, I32, P]
         L.corr_dump.argtypes = [P, I32, P, I32, ctypes.POINTER(I64), ctypes.POINTER(I32)]
         L.corr_ring_read.argtypes = [P, P, I32, ctypes.POINTER(I64)]
         L.corr_stage_read.argtypes = [P, P, P, ctypes.POINTER(I64)]
@@ -176,6 +177,13 @@ def corr_seq_reset(plan: int) -> None:
 def corr_correlate(plan: int, d_samples: int, n_samples: int, row_stride: int = 0) -> None:
     _check(lib().corr_correlate(ctypes.c_void_p(plan), ctypes.c_void_p(d_samples or None), n_samples,
                                 row_stride), "corr_correlate")
+
+
+def corr_correlate_static(cfg: corr_config, d_samples: int, n_samples: int, row_stride: int, d_out: int,
+                          accumulate: bool, stream: int = 0) -> None:
+    _check(lib().corr_correlate_static(ctypes.byref(cfg), ctypes.c_void_p(d_samples or None), n_samples, row_stride,
+                                       ctypes.c_void_p(d_out or None), int(bool(accumulate)),
+                                       ctypes.c_void_p(stream or None)), "corr_correlate_static")
 
 
 def corr_dump(plan: int, what: int, dst: int, dst_is_device: bool):

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcorr.so")
 
-SOURCES = ["corr.cpp", "xengine_i8.hip", "xengine_mfma.hip", "xengine_f32.hip", "accum.hip", "fstage.hip", "frontend.hip", "xengine_designs.hip", "lowp.hip", "sched.cpp"]
+SOURCES = ["corr.cpp", "xengine_i8.hip", "xengine_mfma.hip", "xengine_f32.hip", "accum.hip", "fstage.hip", "frontend.hip", "xengine_designs.hip", "lowp.hip", "sched.cpp", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
