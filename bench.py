@@ -420,23 +420,27 @@ def c1_config(dev, stream):
     from paper_0906_1887_amd import Correlator, perfmodel
     out = {}
 
-    # C1: plain FP32 X-engine, N_I=64, 128 channels, 1000 samples, complex float32
+    # C1: FP32 X-engine, N_I=64, 128 channels, 1000 samples, complex float32
+    # (integer-valued, so both engines are exact): the plain vector engine and
+    # the matrix-core engine
     n_in, n_ch, T = 64, 128, 1000
     x8 = torch.empty((n_ch, n_in, T, 2), dtype=torch.int8, device=dev)
     synth.DeviceGen().fill_ci8(x8.data_ptr(), n_ch, n_in, T, 1, stream=stream.cuda_stream)
     xf = x8.float()
-    c = Correlator(n_in, n_ch, engine="fp32", sample_type="cf32", max_abs=7, device=str(dev))
     cm = perfmodel.xengine_cmac(n_ch, n_in, T)
+    for engine, key, what in (("fp32", "c1_fp32_plain", "plain FP32 vector FMA"),
+                              ("fp32m", "c1_fp32_mfma", "FP32 on the matrix cores (v_mfma_f32_32x32x2_f32)")):
+        c = Correlator(n_in, n_ch, engine=engine, sample_type="cf32", max_abs=7, device=str(dev))
 
-    def c1():
-        c.correlate(xf)
-        c.dump(0)
-    c1()
-    ms = time_events(c1, 200, stream)
-    out["c1_fp32_plain"] = {"ms_per_integration": ms, "tcmac_s": cm / (ms / 1e3) / 1e12,
-                            "frac_of_fp32_peak": cm / (ms / 1e3) / perfmodel.fp32_cmac_peak(),
-                            "note": "X + accumulator reset per integration, 200 back-to-back"}
-    c.close()
+        def c1():
+            c.correlate(xf)
+            c.dump(0)
+        c1()
+        ms = time_events(c1, 200, stream)
+        out[key] = {"ms_per_integration": ms, "tcmac_s": cm / (ms / 1e3) / 1e12,
+                    "frac_of_fp32_peak": cm / (ms / 1e3) / perfmodel.fp32_cmac_peak(),
+                    "engine": what, "note": "X + accumulator reset per integration, 200 back-to-back"}
+        c.close()
     del x8, xf
     return out
 

@@ -78,13 +78,20 @@ typedef enum {
     CORR_X_I8 = 1,            /* int8 MFMA, int32 accumulation (CI8 only)  */
     CORR_X_F16 = 2,           /* FP16 MFMA, FP32 accumulation (CF32 input,
                                  staged unscaled, |x| < 65504)             */
-    CORR_X_F8 = 3             /* OCP FP8 E4M3 MFMA, FP32 accumulation (CF32
+    CORR_X_F8 = 3,            /* OCP FP8 E4M3 MFMA, FP32 accumulation (CF32
                                  input staged with a power-of-two per-channel
                                  scale s_c: the largest with s_c * max|x| <=
                                  448, kept in [2^-60, 2^60]; the epilogue
                                  multiplies by 1/s_c^2).  F16 and F8 plans
                                  with more than 65535 inputs or channels
                                  return CORR_E_UNSUPPORTED.                */
+    CORR_X_FP32M = 4          /* FP32 on the matrix cores
+                                 (v_mfma_f32_32x32x2_f32), FP32 accumulation;
+                                 CF32 input only, no F-stage; rows and base
+                                 16-byte aligned (else corr_correlate returns
+                                 CORR_E_UNSUPPORTED).  Products and sums are
+                                 FP32, in the matrix core's order; exact for
+                                 integer samples under the FP32 bound.     */
 } corr_engine_t;
 
 /* F-stage input formats (corr_config.volt_format). */
@@ -341,14 +348,14 @@ corr_status corr_dump_bytes(const corr_plan *plan, int32_t what, size_t *bytes);
  * memory) and one of 64 queue slots is free.  An admitted job is published
  * on a job queue in the arena's head; a persistent int8 X-engine grid (as
  * many workgroups as the GPU holds at once) takes work items -- (channel,
- * 128-row baseline tile) pairs -- round robin from every published job, so
- * jobs that arrive while others run are taken up by the grid already on the
- * device, and their work overlaps.  No per-job plan is created and no kernel
+ * 128-row baseline tile) pairs -- round robin from every published job
+ * with unclaimed items, so jobs that arrive while others run are taken up by
+ * the grid already on the device, and their work overlaps.  No per-job plan is created and no kernel
  * is launched per job: the grid closes as a whole once the queue has been
  * idle for 0.1 ms, and a new one is launched when work is published after
- * that.  While a grid runs it holds every CU, so other work on the GPU (the
- * per-job path below, fill callbacks) waits for the queue to drain.  The
- * job's device result is complete when its last
+ * that.  A running grid leaves 16 workgroup slots free; other work on the
+ * GPU (the runtime's copies, the per-job path below, fill callbacks) runs
+ * there.  The job's device result is complete when its last
  * item is done (the grid then writes a completion word in pinned host memory
  * that the scheduler polls); a host destination then receives a copy, and
  * the job is complete when that copy has landed (the latency end point).

@@ -9,7 +9,7 @@ from __future__ import annotations
 
 from . import _lib
 from ._lib import (CORR_CF32, CORR_CI4, CORR_CI8, CORR_DUMP_FOLD, CORR_DUMP_INTEG, CORR_DUMP_LONGRUN,
-                   CORR_DUMP_NO_RESET, CORR_X_F8, CORR_X_F16, CORR_X_FP32, CORR_X_I8, CorrError,
+                   CORR_DUMP_NO_RESET, CORR_X_F8, CORR_X_F16, CORR_X_FP32, CORR_X_FP32M, CORR_X_I8, CorrError,
                    corr_aggregate_w16, corr_channelise, corr_cmac_design, corr_config, corr_correlate, corr_create, corr_destroy, corr_dump,
                    corr_dump_bytes, corr_job_desc, corr_ring_read, corr_sched_create, corr_sched_destroy,
                    corr_sched_now, corr_sched_poll, corr_sched_stats, corr_sched_submit, corr_seq_reset,
@@ -24,7 +24,7 @@ __all__ = [
     "corr_cmac_design", "cmac_design", "DESIGNS",
 ]
 
-ENGINES = {"fp32": CORR_X_FP32, "i8": CORR_X_I8, "f16": CORR_X_F16, "f8": CORR_X_F8}
+ENGINES = {"fp32": CORR_X_FP32, "i8": CORR_X_I8, "f16": CORR_X_F16, "f8": CORR_X_F8, "fp32m": CORR_X_FP32M}
 SAMPLE_TYPES = {"cf32": CORR_CF32, "ci8": CORR_CI8, "ci4": CORR_CI4}
 # F-stage input formats: real int8; complex 5+5-bit in 16-bit words; complex 4+4-bit bytes
 VOLT_FORMATS = {"r8": 0, "cw16": 1, "cb8": 2}

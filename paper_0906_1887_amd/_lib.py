@@ -27,6 +27,7 @@ CORR_X_FP32 = 0
 CORR_X_I8 = 1
 CORR_X_F16 = 2
 CORR_X_F8 = 3
+CORR_X_FP32M = 4
 
 CORR_DUMP_INTEG = 1
 CORR_DUMP_LONGRUN = 2

@@ -20,6 +20,7 @@ constexpr int kElemF8 = 2;
 constexpr int kElemCI4 = 3;   // int8 engine on 4-bit complex samples, one byte each
 constexpr int kElemF16Cvt = 4;  // FP16 engine converting complex float32 as it stages
 constexpr int kElemF8Cvt = 5;   // FP8 engine converting (with the per-channel scale) as it stages
+constexpr int kElemF32 = 6;     // complex float32 on v_mfma_f32_32x32x2_f32 (64-row tiles)
 
 __device__ __forceinline__ int64_t xcd_item(int64_t bid, int64_t per_xcd) {
   const int64_t xcd = bid % kNumXcd;
@@ -129,11 +130,13 @@ struct ServeQueue {
   const uint64_t* limit;    // slot s at limit[s * kServeLine / 2]: base + n_items of its job
   uint64_t* claim;          // slot s at claim[s * kServeLine / 2]
   uint32_t* done;           // slot s at done[s * kServeLine]
-  const int32_t* active;    // [1 + n_slots]: count, then the slots holding jobs
+  const int32_t* active;    // [1 + n_slots]: count, then the slots whose jobs have unclaimed items
   uint32_t* rr;             // round-robin counter
   uint64_t* last_claim;     // wall clock (s_memrealtime ticks) of the latest claim or grid start
   uint32_t* closing;        // highest grid generation that has closed (no more claims)
   uint32_t* host_closing;   // the same, in host memory (device view) for the scheduler
+  uint64_t* host_claimed;   // host memory (device view): slot s at [s * kServeLine / 2 + 1] receives
+                            // the claim limit of its job once the job's last item is claimed
   uint32_t gen;             // this launch's generation (increasing from 1)
   uint32_t idle_ticks;      // queue idle this long (100 MHz ticks): the grid closes
   int32_t n_slots;

@@ -56,7 +56,7 @@ int64_t n_products(int64_t n) { return n * (n + 1) / 2; }
 corr_status validate(const corr_config* c) {
   if (!c) return CORR_E_INVAL;
   if (c->n_inputs < 1 || c->n_inputs > 65536 || c->n_channels < 1) return CORR_E_INVAL;
-  if (c->engine < CORR_X_FP32 || c->engine > CORR_X_F8) return CORR_E_INVAL;
+  if (c->engine < CORR_X_FP32 || c->engine > CORR_X_FP32M) return CORR_E_INVAL;
   if (c->sample_type != CORR_CF32 && c->sample_type != CORR_CI8 && c->sample_type != CORR_CI4) return CORR_E_INVAL;
   if (c->sample_type == CORR_CI4) {
     // nibble samples: int8 engine, |re|, |im| <= 7, X-engine input only
@@ -69,6 +69,10 @@ corr_status validate(const corr_config* c) {
     if (c->sample_type != CORR_CF32 || c->max_abs != 0 || c->fft_size != 0) return CORR_E_INVAL;
     if (c->ring_samples < 0) return CORR_E_INVAL;   // 0: convert while staging, no chunked staging buffer
     if (c->n_channels > 65535 || c->n_inputs > 65535) return CORR_E_UNSUPPORTED;
+  }
+  if (c->engine == CORR_X_FP32M) {
+    // complex float32 samples straight into the FP32 matrix cores
+    if (c->sample_type != CORR_CF32 || c->fft_size != 0) return CORR_E_INVAL;
   }
   if (c->engine == CORR_X_I8) {
     if (c->sample_type == CORR_CF32 && c->fft_size == 0) return CORR_E_INVAL;
@@ -101,7 +105,8 @@ Layout layout_of(const corr_config* c) {
   L.n_products = n_products(c->n_inputs);
   // CI4 and the converting FP16/FP8 engines run 128-row tiles only
   const bool lowp_cvt = (c->engine == CORR_X_F16 || c->engine == CORR_X_F8) && c->ring_samples == 0;
-  L.bt = (c->n_inputs > 64 || c->sample_type == CORR_CI4 || lowp_cvt) ? 128 : 64;
+  // the FP32 matrix-core engine runs 64-row tiles only
+  L.bt = c->engine != CORR_X_FP32M && (c->n_inputs > 64 || c->sample_type == CORR_CI4 || lowp_cvt) ? 128 : 64;
   const int64_t nb = (c->n_inputs + L.bt - 1) / L.bt;
   L.n_tiles = (int)(nb * (nb + 1) / 2);
   const int64_t tiles_total = (int64_t)c->n_channels * L.n_tiles;
@@ -256,7 +261,8 @@ corr_status corr_internal_xengine(const corr_xpass* q) {
   a.inv_scale2 = q->inv_scale2;
   a.m_bits = q->m_bits;
   const bool aligned = (a.row_stride_b % 16 == 0) && ((reinterpret_cast<uintptr_t>(q->x) & 15) == 0);
-  if (q->elem == corr::kElemCI4 && !aligned) return CORR_E_UNSUPPORTED;   // nibble rows must be 16-byte aligned
+  // nibble rows and FP32 matrix-core rows are staged 16 bytes at a time
+  if ((q->elem == corr::kElemCI4 || q->elem == corr::kElemF32) && !aligned) return CORR_E_UNSUPPORTED;
   // Off-diagonal tiles first within each XCD (see item_decode) when every XCD
   // gets whole channels and there are off-diagonal tiles.
   a.order = (split == 1 && c.n_channels % corr::kNumXcd == 0 && L.n_tiles > 1) ? 1 : 0;
@@ -474,7 +480,8 @@ corr_status corr_correlate(corr_plan* p, const void* d_samples, int64_t n_sample
       // CI4 sums run at 256 times the visibility inside the engine
       const double i32 = c.sample_type == CORR_CI4 ? 2147483647.0 / 256.0 : 2147483647.0;
       if (c.engine == CORR_X_I8 && !within(c, total, i32)) return CORR_E_OVERFLOW;
-      if (c.engine == CORR_X_FP32 && !within(c, total, 16777216.0)) return CORR_E_OVERFLOW;
+      if ((c.engine == CORR_X_FP32 || c.engine == CORR_X_FP32M) && !within(c, total, 16777216.0))
+        return CORR_E_OVERFLOW;
     }
     if ((c.engine == CORR_X_F16 || c.engine == CORR_X_F8) && c.ring_samples == 0) {
       // Convert while staging (one pass over the float32 samples; FP8 first
@@ -518,7 +525,8 @@ corr_status corr_correlate(corr_plan* p, const void* d_samples, int64_t n_sample
       p->n_accum = total;
       return CORR_OK;
     }
-    const corr_status s = xengine_pass(p, x, sb, n, stride, c.sample_type == CORR_CI4 && d_samples ? corr::kElemCI4 : -1);
+    const int elem = c.engine == CORR_X_FP32M ? corr::kElemF32 : (c.sample_type == CORR_CI4 && d_samples ? corr::kElemCI4 : -1);
+    const corr_status s = xengine_pass(p, x, sb, n, stride, elem);
     if (s != CORR_OK) return s;
     p->n_accum = total;
     if (d_samples == nullptr) p->ring_fill = 0;
@@ -662,7 +670,8 @@ corr_status corr_dump(corr_plan* p, int32_t what, void* dst, int32_t dst_is_devi
       // Integer samples on the exact engines: every integration is exact
       // (corr_correlate refuses anything past the bound); the FP64 long-run
       // sum of exact integers stays exact while 2 max_abs^2 n_long <= 2^53.
-      const bool exact_engine = (c.engine == CORR_X_I8 || c.engine == CORR_X_FP32) && c.max_abs > 0;
+      const bool exact_engine =
+          (c.engine == CORR_X_I8 || c.engine == CORR_X_FP32 || c.engine == CORR_X_FP32M) && c.max_abs > 0;
       const bool long_exact = exact_engine && within(c, p->n_long, 9007199254740992.0);
       *exact_out = (integ && exact_engine) || (longrun && long_exact) ? 1 : 0;
     }

@@ -71,17 +71,28 @@ constexpr int kORow = 20;  // words per channel row of O (16 blocks + pad, 16-by
 // names it as the cure for the FFT's leakage): the input holds TAPS - 1
 // more blocks than there are outputs, and block b's transform input is
 // y_b[n] = sum_p h[p*256 + n] x[(b + p)*256 + n] (weighted overlap-add of
-// TAPS consecutive blocks), formed in the unpack from registers that hold
-// all TAPS blocks of the slot's samples (8 inputs per workgroup).
+// TAPS consecutive blocks).  The workgroup's 16 +
+// TAPS - 1 blocks are each loaded once, as a sliding window: slot f keeps its
+// own block b0 + f in registers, and slots f < TAPS - 1 also load block b0 +
+// 16 + f into LDS (all IN inputs).  For each pair the slots publish their own
+// block's two input bytes in LDS, and slot f reads taps 1 .. TAPS - 1 from
+// there (blocks f + 1 ..) and tap 0 from its registers.
 template <int IN, int TAPS>
 __global__ __launch_bounds__(256, (TAPS > 1 ? 2 : 3)) void fstage_kernel(FArgs a) {
   static_assert(IN == 8 || IN == 16, "inputs per workgroup");
+  // (16 inputs with the filterbank need more than the 256 registers of two
+  // workgroups per CU: measured spills)
   static_assert(TAPS == 1 || IN == 8, "the filterbank path takes 8 inputs per workgroup");
   constexpr int kW = IN / 4;  // words per sample and lane
   __shared__ __attribute__((aligned(16))) float2 S[kFFtPerRound][kFSRow * 16];  // 34 KB
   __shared__ __attribute__((aligned(16))) uint32_t O[kFCh][kORow];              // 10 KB
   __shared__ float2 tw[kFN];                                                     // 2 KB
-  __shared__ float hs[TAPS > 1 ? TAPS * kFN : 1];                                // filterbank: 1 KB per tap
+  // filterbank coefficients by sample: hs[n] = (h[n], h[256 + n], h[512 + n], h[768 + n])
+  __shared__ float4 hs[TAPS > 1 ? kFN : 1];                                      // 4 KB
+  // Filterbank window: the current pair's bytes of blocks b0 .. b0+15 (P,
+  // 16-bit per sample), and all IN inputs of blocks b0+16 .. b0+16+TAPS-2 (Xw).
+  __shared__ __attribute__((aligned(16))) uint16_t P[TAPS > 1 ? kFBlk * kFN : 1];            // 8 KB
+  __shared__ __attribute__((aligned(16))) uint2 Xw[TAPS > 1 ? (TAPS - 1) * kFN : 1];         // 6 KB
 
   const int tid = threadIdx.x;
   // Items run through 4 consecutive block groups of one input group (the
@@ -100,47 +111,63 @@ __global__ __launch_bounds__(256, (TAPS > 1 ? 2 : 3)) void fstage_kernel(FArgs a
   const int l = tid & 15;  // lane within the FFT
   const int64_t nb = min((int64_t)kFBlk, a.n_blocks - b0);
 
-  // Samples t = l + 16 n2 of blocks b0 + f + tp (tp < TAPS), inputs
-  // i0..i0+IN-1 (zero outside).
-  uint32_t w[TAPS][16][kW];
+  // Samples t = l + 16 n2 of block b0 + f (and, filterbank, of block b0 + 16
+  // + f for slots f < TAPS - 1, into Xw), inputs i0..i0+IN-1 (zero outside;
+  // a block is read when some output of this workgroup uses it).
+  uint32_t w[16][kW];
+  constexpr int kLoads = TAPS > 1 ? 2 : 1;
 #pragma unroll
-  for (int tp = 0; tp < TAPS; ++tp) {
+  for (int e = 0; e < kLoads; ++e) {
+    const int j = e == 0 ? f : kFBlk + f;            // block offset from b0
+    if (e == 1 && f >= TAPS - 1) break;
+    const bool need = j < nb + TAPS - 1;
+    uint32_t v[16][kW];
     if (a.vec_in && nb == kFBlk) {
-      const int8_t* p = a.volt + ((b0 + f + tp) * kFN + l) * a.n_in + i0;
+      const int8_t* p = a.volt + ((b0 + j) * kFN + l) * a.n_in + i0;
 #pragma unroll
       for (int n2 = 0; n2 < 16; ++n2) {
         const int8_t* q = p + (int64_t)n2 * 16 * a.n_in;
         if constexpr (IN == 16) {
-          const uint4 v = *reinterpret_cast<const uint4*>(q);
-          w[tp][n2][0] = v.x; w[tp][n2][1] = v.y; w[tp][n2][2] = v.z; w[tp][n2][3] = v.w;
+          const uint4 u = *reinterpret_cast<const uint4*>(q);
+          v[n2][0] = u.x; v[n2][1] = u.y; v[n2][2] = u.z; v[n2][3] = u.w;
         } else {
-          const uint2 v = *reinterpret_cast<const uint2*>(q);
-          w[tp][n2][0] = v.x; w[tp][n2][1] = v.y;
+          const uint2 u = *reinterpret_cast<const uint2*>(q);
+          v[n2][0] = u.x; v[n2][1] = u.y;
         }
       }
     } else {
 #pragma unroll
       for (int n2 = 0; n2 < 16; ++n2) {
-        const int64_t t = (b0 + f + tp) * kFN + l + 16 * n2;
+        const int64_t t = (b0 + j) * kFN + l + 16 * n2;
         const int8_t* p = a.volt + t * a.n_in + i0;
 #pragma unroll
-        for (int j = 0; j < kW; ++j) {
-          uint32_t v = 0;
+        for (int jj = 0; jj < kW; ++jj) {
+          uint32_t u = 0;
           for (int q = 0; q < 4; ++q) {
-            const int i = 4 * j + q;
-            if (f < nb && i0 + i < a.n_in) v |= (uint32_t)(uint8_t)p[i] << (8 * q);
+            const int i = 4 * jj + q;
+            if (need && i0 + i < a.n_in) u |= (uint32_t)(uint8_t)p[i] << (8 * q);
           }
-          w[tp][n2][j] = v;
+          v[n2][jj] = u;
         }
       }
+    }
+    if (e == 0) {
+#pragma unroll
+      for (int n2 = 0; n2 < 16; ++n2)
+#pragma unroll
+        for (int jj = 0; jj < kW; ++jj) w[n2][jj] = v[n2][jj];
+    } else if constexpr (TAPS > 1) {
+#pragma unroll
+      for (int n2 = 0; n2 < 16; ++n2) Xw[f * kFN + l + 16 * n2] = make_uint2(v[n2][0], v[n2][1]);
     }
   }
   // Twiddle table W_256^m; a lane reads W_256^(l k2) for every round from it
   // (the first round's barrier orders these writes before the first read).
   tw[tid] = a.twiddle[tid];
   if constexpr (TAPS > 1) {
-    for (int m = tid; m < TAPS * kFN; m += 256) hs[m] = a.pfb[m];
-    __syncthreads();  // the unpack of the first round reads hs
+    static_assert(TAPS == 4, "hs holds four taps per sample");
+    hs[tid] = make_float4(a.pfb[tid], a.pfb[kFN + tid], a.pfb[2 * kFN + tid], a.pfb[3 * kFN + tid]);
+    __syncthreads();  // hs and Xw are complete
   }
 
   const float h = 0.5f * a.scale;  // the 1/2 of the two-for-one split folded into the scale
@@ -159,23 +186,40 @@ __global__ __launch_bounds__(256, (TAPS > 1 ? 2 : 3)) void fstage_kernel(FArgs a
       const int pr = 4 * g + r;
       // Pass 1: lane n1 = l transforms z[n1 + 16 n2] over n2, z = a + i b.
       float2 x[16], X[16];
+      if constexpr (TAPS == 1) {
 #pragma unroll
-      for (int n2 = 0; n2 < 16; ++n2) {
-        if constexpr (TAPS == 1) {
-          const uint32_t d = w[0][n2][r >> 1];
+        for (int n2 = 0; n2 < 16; ++n2) {
+          const uint32_t d = w[n2][r >> 1];
           if (r & 1)
             x[n2] = make_float2(sbyte<2>(d), sbyte<3>(d));
           else
             x[n2] = make_float2(sbyte<0>(d), sbyte<1>(d));
-        } else {
-          const int n = l + 16 * n2;
-          float xr = 0.f, xi = 0.f;
+        }
+      } else {
+        // publish this slot's block for the pair, then sum the taps
 #pragma unroll
-          for (int tp = 0; tp < TAPS; ++tp) {
-            const uint32_t d = w[tp][n2][r >> 1];
-            const float hv = hs[tp * kFN + n];
-            xr = fmaf(hv, (r & 1) ? sbyte<2>(d) : sbyte<0>(d), xr);
-            xi = fmaf(hv, (r & 1) ? sbyte<3>(d) : sbyte<1>(d), xi);
+        for (int n2 = 0; n2 < 16; ++n2) {
+          const uint32_t d = w[n2][r >> 1];
+          P[f * kFN + l + 16 * n2] = (uint16_t)((r & 1) ? (d >> 16) : (d & 0xFFFFu));
+        }
+        __syncthreads();
+        const uint8_t* Xb = reinterpret_cast<const uint8_t*>(Xw);
+#pragma unroll
+        for (int n2 = 0; n2 < 16; ++n2) {
+          const int n = l + 16 * n2;
+          const uint32_t d = w[n2][r >> 1];
+          const float4 hv4 = hs[n];
+          const float hv[4] = {hv4.x, hv4.y, hv4.z, hv4.w};
+          float xr = fmaf(hv[0], (r & 1) ? sbyte<2>(d) : sbyte<0>(d), 0.f);
+          float xi = fmaf(hv[0], (r & 1) ? sbyte<3>(d) : sbyte<1>(d), 0.f);
+#pragma unroll
+          for (int tp = 1; tp < TAPS; ++tp) {
+            const int j = f + tp;   // block offset from b0
+            const uint32_t u = j < kFBlk ? (uint32_t)P[j * kFN + n]
+                                         : (uint32_t)*reinterpret_cast<const uint16_t*>(
+                                               Xb + ((j - kFBlk) * kFN + n) * 8 + 2 * pr);
+            xr = fmaf(hv[tp], (float)(int8_t)(u & 0xFFu), xr);
+            xi = fmaf(hv[tp], (float)(int8_t)(u >> 8), xi);
           }
           x[n2] = make_float2(xr, xi);
         }
@@ -249,8 +293,8 @@ __global__ __launch_bounds__(256, (TAPS > 1 ? 2 : 3)) void fstage_kernel(FArgs a
     if constexpr (IN == 16) {
 #pragma unroll
       for (int n2 = 0; n2 < 16; ++n2) {
-        w[0][n2][0] = w[0][n2][2];
-        w[0][n2][1] = w[0][n2][3];
+        w[n2][0] = w[n2][2];
+        w[n2][1] = w[n2][3];
       }
     }
   }

@@ -12,15 +12,17 @@
 // of a job queue in the arena's head: its pass (sample and result pointers,
 // shape) and the claim limit of its work items, one per (channel, 128-row
 // baseline tile).  A persistent serving grid (xeng_serve_kernel, as many
-// workgroups as the GPU holds at once) runs while published work remains:
-// every workgroup claims items round robin over the listed jobs, so jobs that
-// arrive while others run are taken up by the grid already on the device and
-// a small job is not queued behind a large one.  Once the queue has been idle
-// for kIdleUs the grid closes as a whole; the scheduler launches a new
-// full-size grid (alternating between two streams, so it can start while the
-// closing one finishes its last tiles) when work is published after the last
-// launch and no open grid is running.  The workgroup that finishes a job's last item writes the job's
-// completion word in pinned host memory.  Results go straight to a device
+// workgroups as the GPU holds at once but kCopyReserve) runs while published
+// work remains.  Its workgroups claim items round robin over the listed jobs,
+// so jobs that arrive while others run are taken up by the grid already on
+// the device and a small job is not queued behind a large one.  A job whose
+// items are all claimed leaves the list.  Once the queue
+// has been idle for kIdleUs the grid closes as a whole; the scheduler
+// launches a new full-size grid (alternating between two streams, so it can
+// start while the closing one finishes its last tiles) when work is published
+// after the last launch and no open grid is running.  The workgroup that
+// finishes a job's last item writes the job's completion word in pinned host
+// memory.  Results go straight to a device
 // destination; a host destination gets the integration through a copy from
 // the arena (the latency end point is then the landed copy).  There is no
 // per-job plan and no per-job kernel launch.
@@ -58,6 +60,10 @@ constexpr int kStage = 512;              // pinned staging entries for queue upd
 constexpr size_t kStageBytes = 512;
 constexpr double kIdleUs = 100.0;        // queue idle this long: the serving grid closes
 constexpr int kMaxPolls = 1 << 18;       // bound on one serving workgroup's empty polls
+constexpr int kCopyStreams = 4;          // streams a large host copy is split over
+constexpr size_t kCopyPart = 32u << 20;  // at least this many bytes per part
+constexpr int kCopyReserve = 16;         // workgroup slots a serving grid leaves free (the runtime's
+                                         // copy kernels for host destinations run there)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -79,6 +85,8 @@ struct Job {
   bool queued_path = true;             // device queue, else per-job plan
   int slot = -1;
   uint64_t items = 0;
+  uint64_t limit = 0;                  // claim limit of the job's items
+  bool claimed_all = false;            // the device has claimed every item
   uint32_t flag_value = 0;
   corr_plan* plan = nullptr;
   int stream = -1;
@@ -187,7 +195,9 @@ struct corr_sched {
   std::vector<int> stream_jobs;            // running per-job-path jobs per stream
   hipStream_t s_ctl = nullptr;             // fills and queue updates
   hipStream_t s_grid[2] = {nullptr, nullptr};  // serving grids, alternately
-  hipStream_t s_copy = nullptr;            // results to host destinations
+  hipStream_t s_copy = nullptr;            // results to host destinations (and the completion callback)
+  hipStream_t s_copy_x[kCopyStreams - 1] = {};  // further parts of large host copies
+  hipEvent_t ev_copy_x[kCopyStreams - 1] = {};
   hipEvent_t ev_pub = nullptr;             // after the latest queue update
   hipEvent_t ev_grid[2] = {nullptr, nullptr};
   bool grid_alive[2] = {false, false};     // launched, completion not yet seen
@@ -256,13 +266,13 @@ hipError_t stage_copy(corr_sched* s, size_t arena_off, const void* src, size_t b
   return r;
 }
 
-// Publish the list of slots holding unfinished jobs (lock held).
+// Publish the list of slots holding jobs with unclaimed items (lock held).
 hipError_t publish_active(corr_sched* s) {
   int32_t list[kSlots + 1];
   int n = 0;
   for (int k = 0; k < kSlots; ++k) {
     const Job* j = s->slot_job[k];
-    if (j && j->state.load() == kRunning) list[1 + n++] = k;
+    if (j && j->state.load() == kRunning && !j->claimed_all) list[1 + n++] = k;
   }
   list[0] = n;
   s->active_dirty = false;
@@ -314,6 +324,7 @@ corr_status launch_queued(corr_sched* s, Job* j) {
   sj.base = s->slot_limit[j->slot];
   s->slot_limit[j->slot] += j->items;
   const uint64_t lim = s->slot_limit[j->slot];
+  j->limit = lim;
   // The job, then its claim limit (a grid claims an item only below the
   // limit, so it sees the job -- and the fill before it -- first), then the
   // list of active slots.
@@ -407,6 +418,17 @@ void retire_job(corr_sched* s, Job* j) {
 void collect_queue(corr_sched* s) {
   for (Job* j : s->running) {
     if (!j->queued_path || j->state.load() != kRunning) continue;
+    if (!j->claimed_all) {
+      const uint64_t c = __atomic_load_n(reinterpret_cast<const uint64_t*>(s->flags) +
+                                             (size_t)j->slot * (corr::kServeLine / 2) + 1,
+                                         __ATOMIC_ACQUIRE);
+      if (c == j->limit) {
+        // every item is claimed: list the job no more, so the grid's
+        // workgroups do not scan past it
+        j->claimed_all = true;
+        s->active_dirty = true;
+      }
+    }
     const uint32_t f = __atomic_load_n(s->flags + (size_t)j->slot * corr::kServeLine, __ATOMIC_ACQUIRE);
     if (f != j->flag_value) continue;
     j->t_device = now_s();
@@ -420,8 +442,23 @@ void collect_queue(corr_sched* s) {
       continue;
     }
     j->state.store(kCopying);
-    hipError_t e = hipMemcpyAsync(j->d.dst, s->arena_base + j->off + j->samples_bytes, j->result_bytes,
-                                  hipMemcpyDeviceToHost, s->s_copy);
+    // A large result goes to the host in up to kCopyStreams parts on as many
+    // streams (copy engines run in parallel); the callback follows them all.
+    const uint8_t* src = s->arena_base + j->off + j->samples_bytes;
+    uint8_t* dst = static_cast<uint8_t*>(j->d.dst);
+    const int parts = (int)std::min<size_t>(kCopyStreams, std::max<size_t>(1, j->result_bytes / kCopyPart));
+    const size_t piece = (j->result_bytes / parts + 255) / 256 * 256;
+    hipError_t e = hipSuccess;
+    for (int k = 1; k < parts && e == hipSuccess; ++k) {
+      const size_t o = k * piece;
+      if (o >= j->result_bytes) break;
+      e = hipMemcpyAsync(dst + o, src + o, std::min(piece, j->result_bytes - o), hipMemcpyDeviceToHost,
+                         s->s_copy_x[k - 1]);
+      if (e == hipSuccess) e = hipEventRecord(s->ev_copy_x[k - 1], s->s_copy_x[k - 1]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s->s_copy, s->ev_copy_x[k - 1], 0);
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dst, src, std::min(piece, j->result_bytes), hipMemcpyDeviceToHost, s->s_copy);
     if (e == hipSuccess) {
       s->callbacks.fetch_add(1);
       e = hipLaunchHostFunc(s->s_copy, on_done, j);
@@ -429,6 +466,7 @@ void collect_queue(corr_sched* s) {
     }
     if (e != hipSuccess) {
       hipStreamSynchronize(s->s_copy);
+      for (hipStream_t x : s->s_copy_x) hipStreamSynchronize(x);
       j->status = CORR_E_HIP;
       j->t_done.store(now_s());
       j->state.store(kDone);
@@ -520,6 +558,10 @@ corr_status corr_sched_create(void* d_arena, size_t arena_bytes, int32_t n_strea
     }
     for (hipStream_t* st : {&s->s_ctl, &s->s_grid[0], &s->s_grid[1], &s->s_copy})
       ok = ok && hipStreamCreateWithFlags(st, hipStreamNonBlocking) == hipSuccess;
+    for (int k = 0; k < kCopyStreams - 1; ++k) {
+      ok = ok && hipStreamCreateWithFlags(&s->s_copy_x[k], hipStreamNonBlocking) == hipSuccess;
+      ok = ok && hipEventCreateWithFlags(&s->ev_copy_x[k], hipEventDisableTiming) == hipSuccess;
+    }
     for (hipEvent_t* e : {&s->ev_pub, &s->ev_grid[0], &s->ev_grid[1]})
       ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
     for (int k = 0; k < kStage && ok; ++k)
@@ -546,17 +588,18 @@ corr_status corr_sched_create(void* d_arena, size_t arena_bytes, int32_t n_strea
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
       cus = 0;   // no serving grid: every job takes the per-job path
-    s->grid_cap = corr::serve_blocks_per_cu() * cus;
+    s->grid_cap = std::max(0, corr::serve_blocks_per_cu() * cus - kCopyReserve);
     s->q.slots = reinterpret_cast<const corr::ServeJob*>(s->arena_base + ql.slots);
     s->q.limit = reinterpret_cast<const uint64_t*>(s->arena_base + ql.limit);
     s->q.claim = reinterpret_cast<uint64_t*>(s->arena_base + ql.claim);
     s->q.done = reinterpret_cast<uint32_t*>(s->arena_base + ql.done);
     s->q.active = reinterpret_cast<const int32_t*>(s->arena_base + ql.active);
-    s->q.rr = reinterpret_cast<uint32_t*>(s->arena_base + ql.rr);
     s->q.n_slots = kSlots;
     s->q.last_claim = reinterpret_cast<uint64_t*>(s->arena_base + ql.last_claim);
     s->q.closing = reinterpret_cast<uint32_t*>(s->arena_base + ql.closing);
     s->q.host_closing = s->d_flags + (size_t)kSlots * corr::kServeLine;
+    s->q.host_claimed = reinterpret_cast<uint64_t*>(s->d_flags);
+    s->q.rr = reinterpret_cast<uint32_t*>(s->arena_base + ql.rr);
     s->q.idle_ticks = (uint32_t)std::max(1.0, (double)clock_khz * 1e3 * kIdleUs * 1e-6);
     s->q.max_polls = kMaxPolls;
     for (int k = kSlots - 1; k >= 0; --k) s->free_slots.push_back(k);
@@ -657,11 +700,15 @@ corr_status corr_sched_destroy(corr_sched* s) {
   std::vector<hipStream_t> all = s->streams;
   for (hipStream_t st : {s->s_ctl, s->s_grid[0], s->s_grid[1], s->s_copy})
     if (st) all.push_back(st);
+  for (hipStream_t st : s->s_copy_x)
+    if (st) all.push_back(st);
   for (hipStream_t st : all) hipStreamSynchronize(st);
   // A callback may still be returning after its stream has passed it.
   while (s->callbacks.load() != 0) std::this_thread::yield();
   for (hipStream_t st : all) hipStreamDestroy(st);
   for (hipEvent_t e : {s->ev_pub, s->ev_grid[0], s->ev_grid[1]})
+    if (e) hipEventDestroy(e);
+  for (hipEvent_t e : s->ev_copy_x)
     if (e) hipEventDestroy(e);
   for (int k = 0; k < kStage; ++k)
     if (s->stage_ev[k]) hipEventDestroy(s->stage_ev[k]);

@@ -59,6 +59,13 @@ __device__ __forceinline__ int rot_f8(int w) {      // two complex fp8 pairs per
 template <int EK>
 __device__ __forceinline__ v4i rot4(v4i v) {
   v4i r;
+  if constexpr (EK == kElemF32) {   // two complex float32 per 16 bytes: (re, im) -> (-im, re)
+    r[0] = (int)((uint32_t)v[1] ^ 0x80000000u);
+    r[1] = v[0];
+    r[2] = (int)((uint32_t)v[3] ^ 0x80000000u);
+    r[3] = v[2];
+    return r;
+  }
 #pragma unroll
   for (int q = 0; q < 4; ++q)
     r[q] = EK == kElemI8 ? rot_i8(v[q]) : (EK == kElemF16 ? rot_f16(v[q]) : rot_f8(v[q]));
@@ -73,6 +80,8 @@ template <>
 struct MAcc<kElemF16> { typedef v16f T; };
 template <>
 struct MAcc<kElemF8> { typedef v16f T; };
+template <>
+struct MAcc<kElemF32> { typedef v16f T; };
 
 // One 64-byte K stage of a 32 x 32 block: fragments are two 16-byte reads per
 // lane (K bytes g*16.. and 32+g*16.., g = lane / 32) of A and of B.
@@ -86,6 +95,16 @@ __device__ __forceinline__ void mfma64(const v4i (&a)[2], const v4i (&b)[2], typ
                                                   acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a[1]), __builtin_bit_cast(v8h, b[1]),
                                                   acc, 0, 0, 0);
+  } else if constexpr (EK == kElemF32) {
+    // 32 x 32 x 2: lanes 0-31 give K element 0 of rows 0-31, lanes 32-63 K
+    // element 1.  Instruction q of half h pairs float q of the lane's chunk
+    // 2h + g (g = lane / 32), so each of the stage's 16 floats enters once,
+    // in the same place for A and B.
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(a[h][q]), __int_as_float(b[h][q]), acc, 0, 0, 0);
   } else {
     const v8i a8 = {a[0][0], a[0][1], a[0][2], a[0][3], a[1][0], a[1][1], a[1][2], a[1][3]};
     const v8i b8 = {b[0][0], b[0][1], b[0][2], b[0][3], b[1][0], b[1][1], b[1][2], b[1][3]};
@@ -1210,12 +1229,14 @@ __global__ __launch_bounds__(256, 2) void xeng_mfma_kernel(XArgs a) {
 
 // Serving: a device queue of integration jobs shared by persistent grids.
 // The host scheduler publishes each admitted job in a slot (its sample and
-// output pointers and shape) and lists the active slots; every workgroup of
-// the running serving grid claims work items -- (channel, 128-row tile)
-// pairs of some job -- from the listed jobs in turn (round robin over the
-// jobs, so a small job is not queued behind a large one), runs the tile over
-// all of the job's samples, and counts it done.  The workgroup that finishes a
-// job's last item writes the job's completion word in host memory.
+// output pointers and shape) and lists the slots whose jobs have unclaimed
+// items; every workgroup of the running serving grid claims work items --
+// (channel, 128-row tile) pairs -- from the listed jobs in turn (round robin
+// over the jobs: a small job is not queued behind a large one, and the claims
+// of the grid's workgroups spread over the jobs' counters), runs the tile
+// over all of the job's samples, and counts it done.  The workgroup that claims a job's last item reports it to
+// the host (which then lists the job no more); the workgroup that finishes
+// the job's last item writes the job's completion word in host memory.
 //
 // A grid ends as a whole: once no workgroup has claimed an item for
 // idle_ticks of the 100 MHz wall clock, the first workgroup to notice closes
@@ -1248,6 +1269,10 @@ __device__ int serve_claim(const ServeQueue& q, uint64_t* claimed) {
                                                    __HIP_MEMORY_SCOPE_AGENT)) {
             __hip_atomic_fetch_max(q.last_claim, (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
+            // the job's last item: tell the host, which then lists the job no more
+            if (w + 1 == lim)
+              __hip_atomic_store(q.host_claimed + (size_t)s * (kServeLine / 2) + 1, lim, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_SYSTEM);
             *claimed = w;
             return s;
           }
@@ -1331,6 +1356,8 @@ hipError_t launch_xeng_mfma(const XArgs& a, int elem, int bt, hipStream_t s) {
 #define CORR_LAUNCH_W2(EK) hipLaunchKernelGGL((xeng_mfma_128_kernel<EK>), g, b, 0, s, a)
   if (elem == kElemI8) {
     if (bt == 128) CORR_LAUNCH_W2(kElemI8); else CORR_LAUNCH(kElemI8, 64);
+  } else if (elem == kElemF32) {
+    CORR_LAUNCH(kElemF32, 64);   // 64-row tiles only
   } else if (elem == kElemCI4) {
     CORR_LAUNCH_W2(kElemCI4);   // 128-row tiles only
   } else if (elem == kElemF16Cvt) {
