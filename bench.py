@@ -241,8 +241,8 @@ def serving(seconds: float, warm: float, rate: float, host: bool, seed: int = 5)
 # WRITE_SIZE runs calibrated against a 1 GiB device copy (FETCH x 2.000,
 # WRITE x 1.000); valid only for the kernel source they were taken on.
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_0906_1887_amd", "csrc", "xengine_mfma.hip")
-TRAFFIC_SHA1 = "23a931191c000bb22e62b266492daaf60755ee25"
-TRAFFIC_BYTES = {"read": 2 * 2.77692e7 * 1024, "write": 3.38402e6 * 1024}
+TRAFFIC_SHA1 = "356abba332c3e2677ea00751425942fcfa810bf8"
+TRAFFIC_BYTES = {"read": 2 * 16998952 * 1024, "write": 3275930 * 1024}
 
 
 def measured_traffic():
