@@ -429,7 +429,7 @@ def c1_config(dev, stream):
     xf = x8.float()
     cm = perfmodel.xengine_cmac(n_ch, n_in, T)
     for engine, key, what in (("fp32", "c1_fp32_plain", "plain FP32 vector FMA"),
-                              ("fp32m", "c1_fp32_mfma", "FP32 on the matrix cores (v_mfma_f32_32x32x2_f32)")):
+                              ("fp32m", "c1_fp32_mfma", "FP32 on the matrix cores (v_mfma_f32_16x16x4_f32)")):
         c = Correlator(n_in, n_ch, engine=engine, sample_type="cf32", max_abs=7, device=str(dev))
 
         def c1():

@@ -86,7 +86,7 @@ typedef enum {
                                  with more than 65535 inputs or channels
                                  return CORR_E_UNSUPPORTED.                */
     CORR_X_FP32M = 4          /* FP32 on the matrix cores
-                                 (v_mfma_f32_32x32x2_f32), FP32 accumulation;
+                                 (v_mfma_f32_16x16x4_f32), FP32 accumulation;
                                  CF32 input only, no F-stage; rows and base
                                  16-byte aligned (else corr_correlate returns
                                  CORR_E_UNSUPPORTED).  Products and sums are

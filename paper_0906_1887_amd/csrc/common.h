@@ -20,7 +20,7 @@ constexpr int kElemF8 = 2;
 constexpr int kElemCI4 = 3;   // int8 engine on 4-bit complex samples, one byte each
 constexpr int kElemF16Cvt = 4;  // FP16 engine converting complex float32 as it stages
 constexpr int kElemF8Cvt = 5;   // FP8 engine converting (with the per-channel scale) as it stages
-constexpr int kElemF32 = 6;     // complex float32 on v_mfma_f32_32x32x2_f32 (64-row tiles)
+constexpr int kElemF32 = 6;     // complex float32 on v_mfma_f32_16x16x4_f32 (64-row tiles)
 
 __device__ __forceinline__ int64_t xcd_item(int64_t bid, int64_t per_xcd) {
   const int64_t xcd = bid % kNumXcd;

@@ -80,8 +80,6 @@ template <>
 struct MAcc<kElemF16> { typedef v16f T; };
 template <>
 struct MAcc<kElemF8> { typedef v16f T; };
-template <>
-struct MAcc<kElemF32> { typedef v16f T; };
 
 // One 64-byte K stage of a 32 x 32 block: fragments are two 16-byte reads per
 // lane (K bytes g*16.. and 32+g*16.., g = lane / 32) of A and of B.
@@ -95,16 +93,6 @@ __device__ __forceinline__ void mfma64(const v4i (&a)[2], const v4i (&b)[2], typ
                                                   acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a[1]), __builtin_bit_cast(v8h, b[1]),
                                                   acc, 0, 0, 0);
-  } else if constexpr (EK == kElemF32) {
-    // 32 x 32 x 2: lanes 0-31 give K element 0 of rows 0-31, lanes 32-63 K
-    // element 1.  Instruction q of half h pairs float q of the lane's chunk
-    // 2h + g (g = lane / 32), so each of the stage's 16 floats enters once,
-    // in the same place for A and B.
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(a[h][q]), __int_as_float(b[h][q]), acc, 0, 0, 0);
   } else {
     const v8i a8 = {a[0][0], a[0][1], a[0][2], a[0][3], a[1][0], a[1][1], a[1][2], a[1][3]};
     const v8i b8 = {b[0][0], b[0][1], b[0][2], b[0][3], b[1][0], b[1][1], b[1][2], b[1][3]};
@@ -1208,12 +1196,189 @@ __global__ __launch_bounds__(256, 1) void xeng_cvt_128_kernel(XArgs a) {
   else mfma_tile_128_cvt<EK, false>(a, lds, ch, split, I, J);
 }
 
+// FP32 matrix-core tile: the 64-row tile of mfma_tile (same staging,
+// pipeline and swizzle), but each wave's 32 x 32 quadrant runs as 2 x 2
+// blocks of v_mfma_f32_16x16x4_f32.  A lane reads one 16-byte chunk (two
+// complex samples) of its block row per stage -- row lane % 16, chunk lane /
+// 16 -- and instruction q takes float q of it from A and from B, so the 16
+// K elements of the stage enter once each, in the same place for both.  In a
+// diagonal tile the quadrant waves skip their strictly upper 16 x 16 block:
+// 2560 products computed per 2080 needed at 64 inputs, against 3072 with
+// 32 x 32 blocks.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <bool DIAG>
+__device__ __forceinline__ void mfma_tile_f32(const XArgs& a, int8_t* lds, int ch, int split, int I, int J) {
+  constexpr int BT = 64;
+  constexpr int PANEL = BT * kMKC;
+  constexpr int STAGE = PANEL * (DIAG ? 1 : 2);
+  constexpr int QPW = BT / 16 / 4;
+  constexpr int LPW = QPW * (DIAG ? 1 : 2);
+
+  const int8_t* __restrict__ xc = static_cast<const int8_t*>(a.x) + (int64_t)ch * a.ch_stride_b;
+  const int64_t k0 = (int64_t)split * a.k_split_bytes;
+  const int64_t k1 = min(a.k_bytes, k0 + a.k_split_bytes);
+  const int n_st = k1 > k0 ? (int)((k1 - k0 + kMKC - 1) / kMKC) : 0;
+  const int64_t last = ((k1 - 1) >> 4) << 4;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const bool wave_idle = DIAG && (wm < wn);
+  const bool quad_diag = DIAG && (wm == wn);
+
+  const int lrow = lane >> 2, p = lane & 3;
+  const int8_t* gA[QPW];
+  const int8_t* gB[QPW];
+  int rowq[QPW];
+#pragma unroll
+  for (int q = 0; q < QPW; ++q) {
+    const int r = (wave * QPW + q) * 16 + lrow;
+    rowq[q] = r;
+    const int c = p ^ swz(r);
+    gA[q] = xc + (int64_t)min(I * BT + r, a.n_in - 1) * a.row_stride_b + 16 * c;
+    if (!DIAG) gB[q] = xc + (int64_t)min(J * BT + r, a.n_in - 1) * a.row_stride_b + 16 * c;
+  }
+  auto issue = [&](int st) {
+    int8_t* base = lds + (st % kMNS) * STAGE;
+    const int64_t kb = k0 + (int64_t)st * kMKC;
+#pragma unroll
+    for (int q = 0; q < QPW; ++q) {
+      const int c = p ^ swz(rowq[q]);
+      const int64_t kk = kb + 16 * c;
+      const int64_t off = (kk <= last ? kb : last - 16 * c);
+      int8_t* dst = base + (wave * QPW + q) * 1024;
+      __builtin_amdgcn_global_load_lds(gA[q] + off, dst, 16, 0, 0);
+      if (!DIAG) __builtin_amdgcn_global_load_lds(gB[q] + off, dst + PANEL, 16, 0, 0);
+    }
+  };
+  auto fix_tail = [&](int st) {
+    int8_t* base = lds + (st % kMNS) * STAGE;
+    const int64_t kb = k0 + (int64_t)st * kMKC;
+#pragma unroll
+    for (int q = 0; q < QPW; ++q) {
+      const int c = p ^ swz(rowq[q]);
+      const int64_t kk = kb + 16 * c;
+      if (kk + 16 > k1) {
+        const int64_t valid = k1 - kk;
+#pragma unroll
+        for (int op = 0; op < (DIAG ? 1 : 2); ++op) {
+          v4i* cell = reinterpret_cast<v4i*>(base + op * PANEL + (wave * QPW + q) * 1024 + lane * 16);
+          v4i v = *cell;
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            const int64_t lo = 4 * w;
+            const int keep = valid >= lo + 4 ? 4 : (valid > lo ? (int)(valid - lo) : 0);
+            const uint32_t m = keep >= 4 ? 0xFFFFFFFFu : ((1u << (8 * keep)) - 1u);
+            v[w] = (int)((uint32_t)v[w] & m);
+          }
+          *cell = v;
+        }
+      }
+    }
+  };
+
+  v4f vr[2][2], vi[2][2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      vr[m][n] = v4f{0.f, 0.f, 0.f, 0.f};
+      vi[m][n] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+
+#pragma unroll
+  for (int s = 0; s < kMNS - 1; ++s)
+    if (s < n_st) issue(s);
+
+  const int frow = lane & 15;
+  const int c4 = lane >> 4;
+  const bool tail = (k1 - k0) % kMKC != 0;
+  for (int s = 0; s < n_st; ++s) {
+    const int ahead = min(kMNS - 2, n_st - 1 - s);
+    if (ahead >= 2) wait_vmcnt<2 * LPW>();
+    else if (ahead == 1) wait_vmcnt<LPW>();
+    else wait_vmcnt<0>();
+    if (tail && s == n_st - 1) {
+      fix_tail(s);
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    }
+    asm volatile("s_barrier" ::: "memory");
+    if (s + kMNS - 1 < n_st) issue(s + kMNS - 1);
+    if (!wave_idle) {
+      const int8_t* As = lds + (s % kMNS) * STAGE;
+      const int8_t* Bs = DIAG ? As : As + PANEL;
+      v4i af[2], bf[2], bj[2];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int r = wm * 32 + m * 16 + frow;
+        af[m] = *reinterpret_cast<const v4i*>(As + r * kMKC + 16 * (c4 ^ swz(r)));
+      }
+#pragma unroll
+      for (int n = 0; n < 2; ++n) {
+        const int r = wn * 32 + n * 16 + frow;
+        bf[n] = *reinterpret_cast<const v4i*>(Bs + r * kMKC + 16 * (c4 ^ swz(r)));
+        bj[n] = rot4<kElemF32>(bf[n]);
+      }
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          if (quad_diag && m < n) continue;   // strictly upper 16 x 16 block
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            vr[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(__int_as_float(af[m][q]), __int_as_float(bf[n][q]),
+                                                            vr[m][n], 0, 0, 0);
+            vi[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(__int_as_float(af[m][q]), __int_as_float(bj[n][q]),
+                                                            vi[m][n], 0, 0, 0);
+          }
+        }
+    }
+  }
+
+  if (wave_idle) return;
+  // Epilogue.  16 x 16 accumulator layout: register r of lane l holds row
+  // 4*(l/16) + r, column l%16.
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      if (quad_diag && m < n) continue;
+      const int j = J * BT + wn * 32 + n * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = I * BT + wm * 32 + m * 16 + 4 * (lane >> 4) + r;
+        if (i < a.n_in && j <= i) {
+          const int64_t off = (int64_t)split * a.out_split_stride + (int64_t)ch * a.n_products + tri_index(i, j);
+          float2* pp = static_cast<float2*>(a.out) + off;
+          const float re = vr[m][n][r];
+          const float im = (i == j) ? 0.f : vi[m][n][r];
+          if (a.accumulate) {
+            float2 o = *pp;
+            o.x += re;
+            o.y += im;
+            *pp = o;
+          } else {
+            *pp = make_float2(re, im);
+          }
+        }
+      }
+    }
+}
+
 // Diagonal or off-diagonal tile of the BT-row engine (one instantiation site
 // for every kernel that runs BT-row tiles).
 template <int EK, int BT>
 __device__ __forceinline__ void mfma_tile_any(const XArgs& a, int8_t* lds, int ch, int split, int I, int J) {
-  if (I == J) mfma_tile<EK, BT, true>(a, lds, ch, split, I, J);
-  else mfma_tile<EK, BT, false>(a, lds, ch, split, I, J);
+  if constexpr (EK == kElemF32) {
+    static_assert(BT == 64, "the FP32 matrix-core engine runs 64-row tiles");
+    if (I == J) mfma_tile_f32<true>(a, lds, ch, split, I, J);
+    else mfma_tile_f32<false>(a, lds, ch, split, I, J);
+  } else {
+    if (I == J) mfma_tile<EK, BT, true>(a, lds, ch, split, I, J);
+    else mfma_tile<EK, BT, false>(a, lds, ch, split, I, J);
+  }
 }
 
 template <int EK, int BT>

@@ -1,5 +1,5 @@
 """GPU parity of the FP32 matrix-core engine (CORR_X_FP32M:
-v_mfma_f32_32x32x2_f32, FP32 accumulation, complex float32 input) through
+v_mfma_f32_16x16x4_f32, FP32 accumulation, complex float32 input) through
 the C ABI.
 
 Integer-valued samples (|re|, |im| <= 7) give exact products and exact FP32
