@@ -73,12 +73,12 @@ constexpr int kORow = 20;  // words per channel row of O (16 blocks + pad, 16-by
 // y_b[n] = sum_p h[p*256 + n] x[(b + p)*256 + n] (weighted overlap-add of
 // TAPS consecutive blocks).  The workgroup's 16 +
 // TAPS - 1 blocks are each loaded once, as a sliding window: slot f keeps its
-// own block b0 + f in registers, and slots f < TAPS - 1 also load block b0 +
-// 16 + f into LDS (all IN inputs).  For each pair the slots publish their own
-// block's two input bytes in LDS, and slot f reads taps 1 .. TAPS - 1 from
-// there (blocks f + 1 ..) and tap 0 from its registers.
+// own block b0 + f in registers, and slots f < TAPS - 1 also block b0 + 16 +
+// f.  For each pair the slots publish those blocks' two input bytes in an LDS
+// window (in the exchange buffer's space), and slot f reads its TAPS taps
+// (blocks f .. f + TAPS - 1) back from there at fixed offsets.
 template <int IN, int TAPS>
-__global__ __launch_bounds__(256, (TAPS > 1 ? 2 : 3)) void fstage_kernel(FArgs a) {
+__global__ __launch_bounds__(256, 3) void fstage_kernel(FArgs a) {
   static_assert(IN == 8 || IN == 16, "inputs per workgroup");
   // (16 inputs with the filterbank need more than the 256 registers of two
   // workgroups per CU: measured spills)
@@ -89,10 +89,12 @@ __global__ __launch_bounds__(256, (TAPS > 1 ? 2 : 3)) void fstage_kernel(FArgs a
   __shared__ float2 tw[kFN];                                                     // 2 KB
   // filterbank coefficients by sample: hs[n] = (h[n], h[256 + n], h[512 + n], h[768 + n])
   __shared__ float4 hs[TAPS > 1 ? kFN : 1];                                      // 4 KB
-  // Filterbank window: the current pair's bytes of blocks b0 .. b0+15 (P,
-  // 16-bit per sample), and all IN inputs of blocks b0+16 .. b0+16+TAPS-2 (Xw).
-  __shared__ __attribute__((aligned(16))) uint16_t P[TAPS > 1 ? kFBlk * kFN : 1];            // 8 KB
-  __shared__ __attribute__((aligned(16))) uint2 Xw[TAPS > 1 ? (TAPS - 1) * kFN : 1];         // 6 KB
+  // Filterbank window: the current pair's two bytes of blocks b0 ..
+  // b0+15+TAPS-1 (re byte then im byte per sample), 9.5 KB in the space of
+  // the exchange buffer S, which the pair's transform uses only after a
+  // barrier that follows the last read of the window.
+  static_assert(TAPS == 1 || (kFBlk + TAPS - 1) * kFN * 2 <= (int)sizeof(S), "the window fits in S");
+  uint16_t* const P = reinterpret_cast<uint16_t*>(&S[0][0]);
 
   const int tid = threadIdx.x;
   // Items run through 4 consecutive block groups of one input group (the
@@ -112,9 +114,10 @@ __global__ __launch_bounds__(256, (TAPS > 1 ? 2 : 3)) void fstage_kernel(FArgs a
   const int64_t nb = min((int64_t)kFBlk, a.n_blocks - b0);
 
   // Samples t = l + 16 n2 of block b0 + f (and, filterbank, of block b0 + 16
-  // + f for slots f < TAPS - 1, into Xw), inputs i0..i0+IN-1 (zero outside;
+  // + f for slots f < TAPS - 1, into wx), inputs i0..i0+IN-1 (zero outside;
   // a block is read when some output of this workgroup uses it).
   uint32_t w[16][kW];
+  uint32_t wx[TAPS > 1 ? 16 : 1][kW];
   constexpr int kLoads = TAPS > 1 ? 2 : 1;
 #pragma unroll
   for (int e = 0; e < kLoads; ++e) {
@@ -158,7 +161,9 @@ __global__ __launch_bounds__(256, (TAPS > 1 ? 2 : 3)) void fstage_kernel(FArgs a
         for (int jj = 0; jj < kW; ++jj) w[n2][jj] = v[n2][jj];
     } else if constexpr (TAPS > 1) {
 #pragma unroll
-      for (int n2 = 0; n2 < 16; ++n2) Xw[f * kFN + l + 16 * n2] = make_uint2(v[n2][0], v[n2][1]);
+      for (int n2 = 0; n2 < 16; ++n2)
+#pragma unroll
+        for (int jj = 0; jj < kW; ++jj) wx[n2][jj] = v[n2][jj];
     }
   }
   // Twiddle table W_256^m; a lane reads W_256^(l k2) for every round from it
@@ -167,7 +172,7 @@ __global__ __launch_bounds__(256, (TAPS > 1 ? 2 : 3)) void fstage_kernel(FArgs a
   if constexpr (TAPS > 1) {
     static_assert(TAPS == 4, "hs holds four taps per sample");
     hs[tid] = make_float4(a.pfb[tid], a.pfb[kFN + tid], a.pfb[2 * kFN + tid], a.pfb[3 * kFN + tid]);
-    __syncthreads();  // hs and Xw are complete
+    __syncthreads();  // hs is complete
   }
 
   const float h = 0.5f * a.scale;  // the 1/2 of the two-for-one split folded into the scale
@@ -196,36 +201,41 @@ __global__ __launch_bounds__(256, (TAPS > 1 ? 2 : 3)) void fstage_kernel(FArgs a
             x[n2] = make_float2(sbyte<0>(d), sbyte<1>(d));
         }
       } else {
-        // publish this slot's block for the pair, then sum the taps
+        // publish this slot's block for the pair (and, slots f < TAPS - 1,
+        // block 16 + f), then sum the taps read back from P: every read of
+        // the lane is at a fixed offset from one base address
 #pragma unroll
         for (int n2 = 0; n2 < 16; ++n2) {
           const uint32_t d = w[n2][r >> 1];
           P[f * kFN + l + 16 * n2] = (uint16_t)((r & 1) ? (d >> 16) : (d & 0xFFFFu));
         }
+        if (f < TAPS - 1) {
+#pragma unroll
+          for (int n2 = 0; n2 < 16; ++n2) {
+            const uint32_t d = wx[n2][r >> 1];
+            P[(kFBlk + f) * kFN + l + 16 * n2] = (uint16_t)((r & 1) ? (d >> 16) : (d & 0xFFFFu));
+          }
+        }
         __syncthreads();
-        const uint8_t* Xb = reinterpret_cast<const uint8_t*>(Xw);
+        const int8_t* Pb = reinterpret_cast<const int8_t*>(P) + (f * kFN + l) * 2;
 #pragma unroll
         for (int n2 = 0; n2 < 16; ++n2) {
-          const int n = l + 16 * n2;
-          const uint32_t d = w[n2][r >> 1];
-          const float4 hv4 = hs[n];
+          const float4 hv4 = hs[l + 16 * n2];
           const float hv[4] = {hv4.x, hv4.y, hv4.z, hv4.w};
-          float xr = fmaf(hv[0], (r & 1) ? sbyte<2>(d) : sbyte<0>(d), 0.f);
-          float xi = fmaf(hv[0], (r & 1) ? sbyte<3>(d) : sbyte<1>(d), 0.f);
+          float xr = 0.f, xi = 0.f;
 #pragma unroll
-          for (int tp = 1; tp < TAPS; ++tp) {
-            const int j = f + tp;   // block offset from b0
-            const uint32_t u = j < kFBlk ? (uint32_t)P[j * kFN + n]
-                                         : (uint32_t)*reinterpret_cast<const uint16_t*>(
-                                               Xb + ((j - kFBlk) * kFN + n) * 8 + 2 * pr);
-            xr = fmaf(hv[tp], (float)(int8_t)(u & 0xFFu), xr);
-            xi = fmaf(hv[tp], (float)(int8_t)(u >> 8), xi);
+          for (int tp = 0; tp < TAPS; ++tp) {
+            const int8_t* q = Pb + (tp * kFN + 16 * n2) * 2;   // block f + tp, sample l + 16 n2
+            xr = fmaf(hv[tp], (float)q[0], xr);
+            xi = fmaf(hv[tp], (float)q[1], xi);
           }
           x[n2] = make_float2(xr, xi);
         }
       }
       dft16(x, X);
-      if (pr == 0) __syncthreads();  // tw is complete
+      // tw is complete (first pair); filterbank: every lane has read the
+      // window before S is written
+      if (TAPS > 1 || pr == 0) __syncthreads();
       S[f][l * kFSRow] = X[0];
 #pragma unroll
       for (int k2 = 1; k2 < 16; ++k2) S[f][l * kFSRow + k2] = cmul(X[k2], tw[(l * k2) & (kFN - 1)]);
