@@ -11,24 +11,69 @@ namespace corr {
 
 // acc[k] = (accumulate ? acc[k] : 0) + part[0][k] + part[1][k] + ... in that
 // order (integer sums are exact; the fixed order keeps float sums
-// reproducible).  n = number of (re, im) pairs per partial buffer.
+// reproducible).  n = number of (re, im) pairs per partial buffer.  A thread
+// takes two neighbouring pairs (wide: one 16-byte load per split, when n is
+// even and both buffers are 16-byte aligned) and issues the loads of four
+// splits before adding them in split order, so several loads are in flight
+// per thread.
+template <typename T2>
+struct Wide;
+template <>
+struct Wide<int2> { typedef int4 T; };
+template <>
+struct Wide<float2> { typedef float4 T; };
+
+template <typename T4>
+__device__ __forceinline__ void add4(T4& s, const T4& p) {
+  s.x += p.x;
+  s.y += p.y;
+  s.z += p.z;
+  s.w += p.w;
+}
+
 template <typename T2>
 __global__ void reduce_splits_kernel(const T2* __restrict__ part, int64_t n, int n_split,
-                                     T2* __restrict__ acc, int accumulate) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                     T2* __restrict__ acc, int accumulate, int wide) {
+  using T4 = typename Wide<T2>::T;
+  const int64_t k = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);   // first pair
   if (k >= n) return;
-  T2 s = part[k];
-  for (int q = 1; q < n_split; ++q) {
-    const T2 p = part[(int64_t)q * n + k];
-    s.x += p.x;
-    s.y += p.y;
+  if (wide) {
+    const T4* __restrict__ p4 = reinterpret_cast<const T4*>(part);
+    const int64_t n4 = n / 2, k4 = k / 2;
+    T4 s = p4[k4];
+    int q = 1;
+    for (; q + 3 < n_split; q += 4) {
+      const T4 a = p4[(int64_t)q * n4 + k4], b = p4[(int64_t)(q + 1) * n4 + k4];
+      const T4 c = p4[(int64_t)(q + 2) * n4 + k4], d = p4[(int64_t)(q + 3) * n4 + k4];
+      add4(s, a);
+      add4(s, b);
+      add4(s, c);
+      add4(s, d);
+    }
+    for (; q < n_split; ++q) add4(s, p4[(int64_t)q * n4 + k4]);
+    T4* __restrict__ a4 = reinterpret_cast<T4*>(acc);
+    if (accumulate) {
+      T4 o = a4[k4];
+      add4(o, s);   // o + s: the same operand order as the pair path below
+      s = o;
+    }
+    a4[k4] = s;
+    return;
   }
-  if (accumulate) {
-    const T2 o = acc[k];
-    s.x = o.x + s.x;
-    s.y = o.y + s.y;
+  for (int64_t kk = k; kk < min(k + 2, n); ++kk) {   // pair by pair
+    T2 s = part[kk];
+    for (int q = 1; q < n_split; ++q) {
+      const T2 p = part[(int64_t)q * n + kk];
+      s.x += p.x;
+      s.y += p.y;
+    }
+    if (accumulate) {
+      const T2 o = acc[kk];
+      s.x = o.x + s.x;
+      s.y = o.y + s.y;
+    }
+    acc[kk] = s;
   }
-  acc[k] = s;
 }
 
 // L[k] += (double) V[k] over n scalars (the (re, im) pairs flattened).
@@ -48,12 +93,16 @@ static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + b
 hipError_t launch_reduce_splits(const void* part, int64_t n_pairs, int n_split, void* acc, int accumulate,
                                 bool is_int, hipStream_t s) {
   if (n_pairs <= 0) return hipSuccess;
+  // two pairs per thread
+  const int64_t threads = (n_pairs + 1) / 2;
+  const int wide = (n_pairs % 2 == 0) && (((reinterpret_cast<uintptr_t>(part) | reinterpret_cast<uintptr_t>(acc)) & 15) == 0);
   if (is_int)
-    hipLaunchKernelGGL(reduce_splits_kernel<int2>, dim3(grid_for(n_pairs, 256)), dim3(256), 0, s,
-                       static_cast<const int2*>(part), n_pairs, n_split, static_cast<int2*>(acc), accumulate);
+    hipLaunchKernelGGL(reduce_splits_kernel<int2>, dim3(grid_for(threads, 256)), dim3(256), 0, s,
+                       static_cast<const int2*>(part), n_pairs, n_split, static_cast<int2*>(acc), accumulate, wide);
   else
-    hipLaunchKernelGGL(reduce_splits_kernel<float2>, dim3(grid_for(n_pairs, 256)), dim3(256), 0, s,
-                       static_cast<const float2*>(part), n_pairs, n_split, static_cast<float2*>(acc), accumulate);
+    hipLaunchKernelGGL(reduce_splits_kernel<float2>, dim3(grid_for(threads, 256)), dim3(256), 0, s,
+                       static_cast<const float2*>(part), n_pairs, n_split, static_cast<float2*>(acc), accumulate,
+                       wide);
   return hipGetLastError();
 }
 

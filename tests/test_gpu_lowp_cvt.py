@@ -14,7 +14,7 @@ product of its group of 8 K elements, so a sum loses at most 8 * 2^-13 of
 its magnitude).
 Cases: input counts around the 128-row tiles, ragged sample counts, rows
 inside wider buffers (16-byte and only 8-byte aligned rows), K-split passes
-with the fused fix-up, accumulation over calls, and the refusal of rows that
+(partials added by the reduction launch), accumulation over calls, and the refusal of rows that
 are not 8-byte aligned."""
 import sys
 
@@ -90,7 +90,7 @@ def test_converting_equals_staged_on_edge_shapes(engine):
 @pytest.mark.parametrize("engine", ["f16", "f8"])
 def test_converting_split_passes_and_accumulation(engine):
     """64 inputs x 128 channels x 1000 samples: a K-split pass (8 splits, the
-    last split of each tile adds the partials); then the same samples in two
+    reduction launch adds the partials in split order); then the same samples in two
     calls into one integration, against the staged plan fed the same two calls
     (FP8: each call takes the scale of its own samples)."""
     n_in, n_ch, T = 64, 128, 1000
