@@ -65,6 +65,14 @@ __device__ __forceinline__ float sbyte(uint32_t w) {
 // S[f] is used by the 16 lanes of slot f only, all in one wave; O is the
 // workgroup's corner turn for the current pair.
 constexpr int kORow = 20;  // words per channel row of O (16 blocks + pad, 16-byte aligned rows)
+constexpr int kPRow = kFN + 16;  // words per block of the filterbank window (a wave's 4 slots on distinct banks)
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+// (re, im) bytes in the low 16 bits of v -> two binary16 in one word.
+__device__ __forceinline__ uint32_t pair_f16(uint32_t v) {
+  // exact: |values| <= 128
+  return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(sbyte<0>(v), sbyte<1>(v)));
+}
 
 //
 // TAPS > 1: polyphase filterbank in place of the plain transform (Sec. 6.1
@@ -74,9 +82,11 @@ constexpr int kORow = 20;  // words per channel row of O (16 blocks + pad, 16-by
 // TAPS consecutive blocks).  The workgroup's 16 +
 // TAPS - 1 blocks are each loaded once, as a sliding window: slot f keeps its
 // own block b0 + f in registers, and slots f < TAPS - 1 also block b0 + 16 +
-// f.  For each pair the slots publish those blocks' two input bytes in an LDS
-// window (in the exchange buffer's space), and slot f reads its TAPS taps
-// (blocks f .. f + TAPS - 1) back from there at fixed offsets.
+// f.  For each pair the slots publish those blocks' two samples in an LDS
+// window (in the exchange buffer's space) as binary16 pairs (exact for 8-bit
+// integers), and slot f reads its TAPS taps (blocks f .. f + TAPS - 1) back
+// from there at fixed offsets: one 4-byte read and two mixed-precision FMAs
+// (binary16 operand, FP32 product and sum) per tap and sample.
 template <int IN, int TAPS>
 __global__ __launch_bounds__(256, 3) void fstage_kernel(FArgs a) {
   static_assert(IN == 8 || IN == 16, "inputs per workgroup");
@@ -89,12 +99,12 @@ __global__ __launch_bounds__(256, 3) void fstage_kernel(FArgs a) {
   __shared__ float2 tw[kFN];                                                     // 2 KB
   // filterbank coefficients by sample: hs[n] = (h[n], h[256 + n], h[512 + n], h[768 + n])
   __shared__ float4 hs[TAPS > 1 ? kFN : 1];                                      // 4 KB
-  // Filterbank window: the current pair's two bytes of blocks b0 ..
-  // b0+15+TAPS-1 (re byte then im byte per sample), 9.5 KB in the space of
-  // the exchange buffer S, which the pair's transform uses only after a
-  // barrier that follows the last read of the window.
-  static_assert(TAPS == 1 || (kFBlk + TAPS - 1) * kFN * 2 <= (int)sizeof(S), "the window fits in S");
-  uint16_t* const P = reinterpret_cast<uint16_t*>(&S[0][0]);
+  // Filterbank window: the current pair's samples of blocks b0 ..
+  // b0+15+TAPS-1 (binary16 re, im per sample), 20 KB in the space of the
+  // exchange buffer S, which the pair's transform uses only after a barrier
+  // that follows the last read of the window.
+  static_assert(TAPS == 1 || (kFBlk + TAPS - 1) * kPRow * 4 <= (int)sizeof(S), "the window fits in S");
+  uint32_t* const P = reinterpret_cast<uint32_t*>(&S[0][0]);
 
   const int tid = threadIdx.x;
   // Items run through 4 consecutive block groups of one input group (the
@@ -207,17 +217,17 @@ __global__ __launch_bounds__(256, 3) void fstage_kernel(FArgs a) {
 #pragma unroll
         for (int n2 = 0; n2 < 16; ++n2) {
           const uint32_t d = w[n2][r >> 1];
-          P[f * kFN + l + 16 * n2] = (uint16_t)((r & 1) ? (d >> 16) : (d & 0xFFFFu));
+          P[f * kPRow + l + 16 * n2] = pair_f16((r & 1) ? (d >> 16) : d);
         }
         if (f < TAPS - 1) {
 #pragma unroll
           for (int n2 = 0; n2 < 16; ++n2) {
             const uint32_t d = wx[n2][r >> 1];
-            P[(kFBlk + f) * kFN + l + 16 * n2] = (uint16_t)((r & 1) ? (d >> 16) : (d & 0xFFFFu));
+            P[(kFBlk + f) * kPRow + l + 16 * n2] = pair_f16((r & 1) ? (d >> 16) : d);
           }
         }
         __syncthreads();
-        const int8_t* Pb = reinterpret_cast<const int8_t*>(P) + (f * kFN + l) * 2;
+        const uint32_t* Pb = P + f * kPRow + l;
 #pragma unroll
         for (int n2 = 0; n2 < 16; ++n2) {
           const float4 hv4 = hs[l + 16 * n2];
@@ -225,9 +235,10 @@ __global__ __launch_bounds__(256, 3) void fstage_kernel(FArgs a) {
           float xr = 0.f, xi = 0.f;
 #pragma unroll
           for (int tp = 0; tp < TAPS; ++tp) {
-            const int8_t* q = Pb + (tp * kFN + 16 * n2) * 2;   // block f + tp, sample l + 16 n2
-            xr = fmaf(hv[tp], (float)q[0], xr);
-            xi = fmaf(hv[tp], (float)q[1], xi);
+            // block f + tp, sample l + 16 n2
+            const half2_t q = __builtin_bit_cast(half2_t, Pb[tp * kPRow + 16 * n2]);
+            xr = fmaf(hv[tp], (float)q.x, xr);
+            xi = fmaf(hv[tp], (float)q.y, xi);
           }
           x[n2] = make_float2(xr, xi);
         }
