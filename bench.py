@@ -241,8 +241,8 @@ def serving(seconds: float, warm: float, rate: float, host: bool, seed: int = 5)
 # WRITE_SIZE runs calibrated against a 1 GiB device copy (FETCH x 2.000,
 # WRITE x 1.000); valid only for the kernel source they were taken on.
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_0906_1887_amd", "csrc", "xengine_mfma.hip")
-TRAFFIC_SHA1 = "356abba332c3e2677ea00751425942fcfa810bf8"
-TRAFFIC_BYTES = {"read": 2 * 16998952 * 1024, "write": 3275930 * 1024}
+TRAFFIC_SHA1 = "e038011f8782945050b1fac0816841b0765e2170"
+TRAFFIC_BYTES = {"read": 2 * 16533686 * 1024, "write": 3274530 * 1024}
 
 
 def measured_traffic():
