@@ -58,7 +58,14 @@ typedef enum {
     CORR_E_OVERFLOW = -5,     /* accumulation would exceed the int32/FP32 bound */
     CORR_E_SEQ = -6,          /* sample-block sequence gap or duplicate   */
     CORR_E_BUSY = -7,         /* ring buffer full / result not ready      */
-    CORR_E_UNSUPPORTED = -8   /* valid request this build does not handle */
+    CORR_E_UNSUPPORTED = -8,  /* valid request this build does not handle */
+    CORR_E_CORRUPT = -9,      /* a workspace guard band was overwritten (a
+                                 kernel wrote outside its region); the plan
+                                 is now in error                          */
+    CORR_STATUS_MIN_ = -2147483647 - 1  /* never returned: gives the enum the
+                                 whole int32 range, so that any int a caller
+                                 passes to corr_status_str is a value of the
+                                 type in C++ as in C                        */
 } corr_status;
 
 typedef enum {
@@ -152,7 +159,11 @@ typedef struct {
                                  fft_size is 0                               */
 } corr_config;
 
-/* Bytes of device workspace a plan needs for `cfg`.  Host only. */
+/* Bytes of device workspace a plan needs for `cfg`.  Host only.  The
+ * workspace holds the plan's regions, the integration accumulator first (at
+ * offset 0, [n_channels][P][2]), each region padded to 256 bytes and followed
+ * by a 256-byte guard band; its last 256 bytes hold the guard check's result
+ * (race and overrun detection: see corr_dump). */
 corr_status corr_workspace_bytes(const corr_config *cfg, size_t *bytes);
 
 /* Validate `cfg`, carve the caller's workspace (device pointer, >= the size
@@ -309,7 +320,10 @@ corr_status corr_correlate_static(const corr_config *cfg, const void *d_samples,
  * dividing by *n_samples_out is the caller's choice.  Synchronises the
  * plan's stream, so device faults surface here as CORR_E_HIP -- except for a
  * plain reset (no INTEG, LONGRUN or FOLD flag), which queues nothing and
- * returns at once.
+ * returns at once.  A dump that waits also checks the workspace's guard
+ * bands (filled with a fixed pattern before the plan's first kernel): a band
+ * that changed means some kernel wrote outside its region, and the dump
+ * returns CORR_E_CORRUPT (the copy has been made; the plan is in error).
  * *n_samples_out: time samples accumulated in the integration (before reset).
  * *exact_out: 1 if every sum copied to dst is provably exact, else 0: for
  * INTEG, integer samples on the int8 or FP32 engine (within the bounds

@@ -18,6 +18,7 @@ CORR_E_OVERFLOW = -5
 CORR_E_SEQ = -6
 CORR_E_BUSY = -7
 CORR_E_UNSUPPORTED = -8
+CORR_E_CORRUPT = -9
 
 CORR_CF32 = 0
 CORR_CI8 = 1

@@ -125,4 +125,44 @@ hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Guard word w of band g: a position-dependent pattern, so that a band copied
+// or shifted onto another is also seen.
+__device__ __forceinline__ uint32_t guard_word(int g, int w) {
+  return 0xA5C3F00Du ^ ((uint32_t)(g * (kGuardBytes / 4) + w) * 0x9E3779B1u);
+}
+
+__global__ void guard_fill_kernel(uint8_t* __restrict__ ws, GuardList gl) {
+  const int g = blockIdx.x, w = threadIdx.x;   // one block per band, one thread per word
+  reinterpret_cast<uint32_t*>(ws + gl.off[g])[w] = guard_word(g, w);
+}
+
+// One workgroup: count the band words that differ from the pattern.
+__global__ void guard_check_kernel(const uint8_t* __restrict__ ws, GuardList gl, uint32_t* __restrict__ bad) {
+  __shared__ uint32_t count;
+  if (threadIdx.x == 0) count = 0;
+  __syncthreads();
+  constexpr int kWords = kGuardBytes / 4;
+  uint32_t n = 0;
+  for (int k = threadIdx.x; k < gl.n * kWords; k += blockDim.x) {
+    const int g = k / kWords, w = k % kWords;
+    n += reinterpret_cast<const uint32_t*>(ws + gl.off[g])[w] != guard_word(g, w) ? 1u : 0u;
+  }
+  if (n) atomicAdd(&count, n);
+  __syncthreads();
+  if (threadIdx.x == 0) *bad = count;
+}
+
+hipError_t launch_guard_fill(uint8_t* ws, const GuardList& g, hipStream_t s) {
+  if (g.n <= 0) return hipSuccess;
+  if (g.n > kMaxGuards) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(guard_fill_kernel, dim3(g.n), dim3(kGuardBytes / 4), 0, s, ws, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_guard_check(const uint8_t* ws, const GuardList& g, uint32_t* bad, hipStream_t s) {
+  if (g.n > kMaxGuards) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(guard_check_kernel, dim3(1), dim3(256), 0, s, ws, g, bad);
+  return hipGetLastError();
+}
+
 }  // namespace corr

@@ -49,6 +49,8 @@ struct Layout {
   int n_tiles = 0;
   int64_t ring_stride = 0;
   int64_t n_products = 0;
+  corr::GuardList guards{};            // a guard band after each region
+  size_t status = 0;                   // 256 bytes: the guard check's result word
 };
 
 int64_t n_products(int64_t n) { return n * (n + 1) / 2; }
@@ -115,26 +117,32 @@ Layout layout_of(const corr_config* c) {
                     : (int)std::min<int64_t>(kMaxSplit, (kTargetItems + tiles_total - 1) / tiles_total);
   const size_t pair_bytes = 8;  // int2 (int8 engine) or float2 (others)
   size_t off = 0;
+  // each region is followed by a guard band (checked by corr_dump)
+  auto end_region = [&](size_t bytes) {
+    off = align_up(off + bytes, kAlign);
+    L.guards.off[L.guards.n++] = off;
+    off += corr::kGuardBytes;
+  };
   L.acc = off;
   L.acc_bytes = (size_t)c->n_channels * L.n_products * pair_bytes;
-  off = align_up(off + L.acc_bytes, kAlign);
+  end_region(L.acc_bytes);
   if (c->fp64_longrun) {
     L.longrun = off;
     L.longrun_bytes = (size_t)c->n_channels * L.n_products * 16;
-    off = align_up(off + L.longrun_bytes, kAlign);
+    end_region(L.longrun_bytes);
   }
   if (c->fft_size != 0) {
     L.ring_stride = (c->ring_samples + 63) / 64 * 64;
     L.ring = off;
     L.ring_bytes = (size_t)c->n_channels * c->n_inputs * L.ring_stride * 2;
-    off = align_up(off + L.ring_bytes, kAlign);
+    end_region(L.ring_bytes);
     L.tw = off;
     L.tw_bytes = (size_t)c->fft_size * sizeof(float2);
-    off = align_up(off + L.tw_bytes, kAlign);
+    end_region(L.tw_bytes);
     if (c->pfb_taps > 1) {
       L.pfb = off;
       L.pfb_bytes = (size_t)c->pfb_taps * c->fft_size * sizeof(float);
-      off = align_up(off + L.pfb_bytes, kAlign);
+      end_region(L.pfb_bytes);
     }
   }
   if (c->engine == CORR_X_F16 || c->engine == CORR_X_F8) {
@@ -142,18 +150,19 @@ Layout layout_of(const corr_config* c) {
     L.stage_stride = (c->ring_samples + 63) / 64 * 64;
     L.stage = off;
     L.stage_bytes = (size_t)c->n_channels * c->n_inputs * L.stage_stride * L.stage_sb;   // 0 when converting
-    off = align_up(off + L.stage_bytes, kAlign);
+    end_region(L.stage_bytes);
     L.mbits = off;
-    off = align_up(off + (size_t)c->n_channels * 4, kAlign);
+    end_region((size_t)c->n_channels * 4);
     L.scales = off;
-    off = align_up(off + (size_t)c->n_channels * 4, kAlign);
+    end_region((size_t)c->n_channels * 4);
   }
   if (L.max_split > 1) {
     L.part = off;
     L.part_bytes = (size_t)L.max_split * L.acc_bytes;
-    off = align_up(off + L.part_bytes, kAlign);
+    end_region(L.part_bytes);
   }
-  L.total = std::max<size_t>(off, kAlign);
+  L.status = off;
+  L.total = off + kAlign;
   return L;
 }
 
@@ -171,6 +180,7 @@ struct corr_plan {
   bool acc_zero = true;      // accumulator logically zero (contents stale)
   bool error = false;
   bool seq_valid = false;
+  bool guards_set = false;   // the workspace's guard bands hold their pattern
   uint64_t next_seq = 0;
   int64_t ring_fill = 0;     // samples waiting in the ring
   int64_t stage_fill = 0;    // samples of the last FP16/FP8 staged chunk
@@ -185,6 +195,14 @@ corr_status hip_fail(corr_plan* p, hipError_t e) {
 }
 
 void* at(corr_plan* p, size_t off) { return p->ws + off; }
+
+// Fill the guard bands before the plan's first kernel writes its workspace.
+hipError_t ensure_guards(corr_plan* p) {
+  if (p->guards_set) return hipSuccess;
+  const hipError_t e = corr::launch_guard_fill(p->ws, p->L.guards, p->stream);
+  if (e == hipSuccess) p->guards_set = true;
+  return e;
+}
 
 // Launch one X-engine pass over samples [n_ch][n_in][row_stride] (bytes per
 // sample `sb`), n_samples per row, into the plan's accumulator.
@@ -307,6 +325,7 @@ const char* corr_status_str(corr_status s) {
     case CORR_E_SEQ: return "sample block sequence gap or duplicate";
     case CORR_E_BUSY: return "ring buffer full or result not ready";
     case CORR_E_UNSUPPORTED: return "unsupported configuration";
+    case CORR_E_CORRUPT: return "a workspace guard band was overwritten";
   }
   return "unknown status";
 }
@@ -419,6 +438,8 @@ corr_status corr_channelise(corr_plan* p, const void* d_volt, int64_t n_blocks, 
     if (p->seq_valid && first_seq != p->next_seq) return CORR_E_SEQ;
     if (p->ring_fill + n_blocks > c.ring_samples) return CORR_E_BUSY;
     if (n_blocks > 0) {
+      const hipError_t eg = ensure_guards(p);
+      if (eg != hipSuccess) return hip_fail(p, eg);
       corr::FStageCall fc;
       fc.volt = d_volt;
       fc.twiddle = static_cast<const float2*>(at(p, p->L.tw));
@@ -482,6 +503,10 @@ corr_status corr_correlate(corr_plan* p, const void* d_samples, int64_t n_sample
       if (c.engine == CORR_X_I8 && !within(c, total, i32)) return CORR_E_OVERFLOW;
       if ((c.engine == CORR_X_FP32 || c.engine == CORR_X_FP32M) && !within(c, total, 16777216.0))
         return CORR_E_OVERFLOW;
+    }
+    if (n > 0) {
+      const hipError_t eg = ensure_guards(p);
+      if (eg != hipSuccess) return hip_fail(p, eg);
     }
     if ((c.engine == CORR_X_F16 || c.engine == CORR_X_F8) && c.ring_samples == 0) {
       // Convert while staging (one pass over the float32 samples; FP8 first
@@ -660,9 +685,21 @@ corr_status corr_dump(corr_plan* p, int32_t what, void* dst, int32_t dst_is_devi
       if (e != hipSuccess) return hip_fail(p, e);
     }
     // A plain reset (no copy, no fold) queues nothing and need not wait.
+    // Dumps that wait also check the workspace's guard bands.
+    uint32_t bad = 0;
     if (integ || longrun || fold) {
+      if (p->guards_set) {
+        uint32_t* word = static_cast<uint32_t*>(at(p, L.status));
+        e = corr::launch_guard_check(p->ws, L.guards, word, p->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&bad, word, sizeof(bad), hipMemcpyDeviceToHost, p->stream);
+        if (e != hipSuccess) return hip_fail(p, e);
+      }
       e = hipStreamSynchronize(p->stream);
       if (e != hipSuccess) return hip_fail(p, e);
+      if (bad != 0) {
+        p->error = true;
+        return CORR_E_CORRUPT;
+      }
     }
     if (integ && p->acc_zero && !dst_is_device) std::memset(dst, 0, L.acc_bytes);
     if (n_samples_out) *n_samples_out = p->n_accum;

@@ -25,6 +25,18 @@ hipError_t launch_reduce_splits(const void* part, int64_t n_pairs, int n_split, 
 hipError_t launch_fold_f64(double* L, const void* V, int64_t n_scalars, bool is_int, hipStream_t s);
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
 
+// Guard bands of a plan's workspace: kGuardBytes after each region, filled
+// with a pattern that depends on the band and the word, and compared later.
+constexpr int kGuardBytes = 256;
+constexpr int kMaxGuards = 12;
+struct GuardList {
+  uint64_t off[kMaxGuards];   // byte offsets of the bands in the workspace (256-byte aligned)
+  int32_t n;
+};
+hipError_t launch_guard_fill(uint8_t* ws, const GuardList& g, hipStream_t s);
+// Writes the number of guard words that differ from the pattern to *bad.
+hipError_t launch_guard_check(const uint8_t* ws, const GuardList& g, uint32_t* bad, hipStream_t s);
+
 struct FStageCall {
   const void* volt;        // real int8 (format 0), 16-bit 5+5 words (1) or 4+4 bytes (2)
   const float2* twiddle;

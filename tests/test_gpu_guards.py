@@ -1,0 +1,98 @@
+"""Workspace guard bands on the GPU, through the C ABI.
+
+Each region of a plan's workspace is followed by a 256-byte guard band that
+the plan fills with a fixed pattern before its first kernel; a dump that
+waits for the stream compares every band with the pattern and returns
+CORR_E_CORRUPT when one changed (some kernel wrote outside its region).
+Every other GPU test dumps through this check, so the whole suite also shows
+that no engine writes past its regions.  Here the failure is forced from the
+host: one byte is changed, by a torch kernel on the plan's stream, in the
+band after the integration accumulator (which starts the workspace) and in
+the last band (before the workspace's final 256 bytes), and the dump must
+report it and leave the plan in error."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_0906_1887_amd import CORR_DUMP_INTEG, CorrError, Correlator, _lib
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def plant_and_dump(c, x, offset):
+    c.correlate(x)
+    out, n, exact = c.dump(CORR_DUMP_INTEG, device_out=False)      # bands intact
+    c.correlate(x)
+    band = c.workspace[offset:offset + 1]
+    band.add_(1)                                                     # one byte of a band changes
+    with pytest.raises(CorrError) as e:
+        c.dump(CORR_DUMP_INTEG, device_out=False)
+    assert e.value.status == _lib.CORR_E_CORRUPT
+    with pytest.raises(CorrError) as e:
+        c.correlate(x)
+    assert e.value.status == _lib.CORR_E_STATE                      # the plan is in error
+    return out
+
+
+def test_band_after_the_accumulator():
+    n_in, n_ch, T = 40, 3, 300
+    xn = synth.ci8(seed=41, n_channels=n_ch, n_inputs=n_in, n_samples=T)
+    x = torch.from_numpy(xn).to(DEV)
+    c = Correlator(n_in, n_ch, engine="i8", max_abs=7, device=DEV)
+    acc_bytes = n_ch * (n_in * (n_in + 1) // 2) * 8
+    band = (acc_bytes + 255) // 256 * 256
+    say(f"[guards] band after the accumulator at byte {band} of {c.ws_bytes}")
+    out = plant_and_dump(c, x, band)
+    assert np.array_equal(out.numpy().astype(np.int64), oracle.xengine_ci8(xn))
+    c.close()
+
+
+@pytest.mark.parametrize("engine,sample_type,max_abs", [("i8", "ci8", 7), ("fp32m", "cf32", 7)])
+def test_last_band(engine, sample_type, max_abs):
+    # 64 inputs x 16 channels: K-split partials, the last region before the final band
+    n_in, n_ch, T = 64, 16, 1000
+    xn = synth.ci8(seed=42, n_channels=n_ch, n_inputs=n_in, n_samples=T)
+    x = torch.from_numpy(xn if sample_type == "ci8" else xn.astype(np.float32)).to(DEV)
+    c = Correlator(n_in, n_ch, engine=engine, sample_type=sample_type, max_abs=max_abs, device=DEV)
+    say(f"[guards] {engine}: last band at byte {c.ws_bytes - 512} of {c.ws_bytes}")
+    out = plant_and_dump(c, x, c.ws_bytes - 512)
+    assert np.array_equal(out.numpy().astype(np.int64), oracle.xengine_ci8(xn))
+    c.close()
+
+
+def test_bands_hold_through_every_engine_and_the_fstage():
+    """Plans whose kernels run right up to their regions' ends (ragged tiles,
+    K splits, staged FP16/FP8 chunks, the F-stage ring and the filterbank)
+    dump without CORR_E_CORRUPT."""
+    n_in, n_ch, T = 129, 5, 333
+    xi = torch.from_numpy(synth.ci8(seed=43, n_channels=n_ch, n_inputs=n_in, n_samples=T)).to(DEV)
+    xf = torch.from_numpy(np.stack([synth.complex_float(44, ch, n_in, T) for ch in range(n_ch)])).to(DEV)
+    for engine, st, x, m, ring in (("i8", "ci8", xi, 7, 0), ("fp32", "ci8", xi, 7, 0), ("fp32", "cf32", xf, 0, 0),
+                                   ("f16", "cf32", xf, 0, 100), ("f8", "cf32", xf, 0, 100), ("f16", "cf32", xf, 0, 0),
+                                   ("f8", "cf32", xf, 0, 0)):
+        say(f"[guards] {engine} {st} ring={ring}")
+        c = Correlator(n_in, n_ch, engine=engine, sample_type=st, max_abs=m, ring_samples=ring, device=DEV)
+        c.correlate(x)
+        c.dump(CORR_DUMP_INTEG, device_out=True)
+        c.close()
+    s = float(np.float32(0.011))
+    for taps in (0, 4):
+        say(f"[guards] F-stage, {taps} taps")
+        nb = 37
+        v = torch.from_numpy(synth.real_voltages(seed=45, index=0, n_blocks=nb + max(taps - 1, 0), n_inputs=24)).to(DEV)
+        c = Correlator(24, 128, engine="i8", fft_size=256, max_abs=7, requant_scale=s, ring_samples=nb,
+                       fp64_longrun=True, pfb_taps=taps, device=DEV)
+        c.channelise(v, first_seq=0)
+        c.correlate(None)
+        c.dump(CORR_DUMP_INTEG | 4, device_out=True)                 # fold into the long-run sum too
+        c.close()
