@@ -258,6 +258,24 @@ corr_status corr_cmac_design(int32_t design, int32_t group, const float *d_spect
 /* Accept any first_seq on the next corr_channelise call. */
 corr_status corr_seq_reset(corr_plan *plan);
 
+/* Checkpoint and resume of a long run (Fig. 1: visibilities dumped after
+ * each interval and kept; Sec. 5: continuous operation).  What a plan needs
+ * to continue is its FP64 long-run sum (corr_dump with CORR_DUMP_LONGRUN),
+ * the number of samples folded into it and the F-stage's next block
+ * sequence number; the integration accumulator and the ring are not kept.
+ * corr_state writes those two numbers (*seq_valid 0: no block seen since
+ * creation or corr_seq_reset).  Host only; any out pointer may be NULL. */
+corr_status corr_state(const corr_plan *plan, int64_t *n_long, uint64_t *next_seq, int32_t *seq_valid);
+
+/* Load a checkpoint into a plan with the same configuration (and
+ * fp64_longrun set): the long-run sum from `longrun` ([n_channels][P][2]
+ * float64, host memory if src_is_device == 0, else device), the sample count
+ * n_long (>= 0) and the sequence state.  The integration accumulator and the
+ * ring are emptied.  Synchronises the plan's stream.  CORR_E_INVAL for a plan
+ * without a long-run sum or a NULL source; CORR_E_STATE for a plan in error. */
+corr_status corr_restore(corr_plan *plan, const void *longrun, int32_t src_is_device, int64_t n_long,
+                         uint64_t next_seq, int32_t seq_valid);
+
 /* X-engine (Sec. 4 "third step"): for every channel and every pair j <= i,
  * add sum over the n_samples time samples of x_i conj(x_j) to the plan's
  * integration accumulator.

@@ -12,8 +12,8 @@ from ._lib import (CORR_CF32, CORR_CI4, CORR_CI8, CORR_DUMP_FOLD, CORR_DUMP_INTE
                    CORR_DUMP_NO_RESET, CORR_X_F8, CORR_X_F16, CORR_X_FP32, CORR_X_FP32M, CORR_X_I8, CorrError,
                    corr_aggregate_w16, corr_channelise, corr_cmac_design, corr_config, corr_correlate, corr_create, corr_destroy, corr_dump,
                    corr_dump_bytes, corr_job_desc, corr_ring_read, corr_sched_create, corr_sched_destroy,
-                   corr_sched_now, corr_sched_poll, corr_sched_stats, corr_sched_submit, corr_seq_reset,
-                   corr_stage_read, corr_status_str, corr_workspace_bytes)
+                   corr_restore, corr_sched_now, corr_sched_poll, corr_sched_stats, corr_sched_submit,
+                   corr_seq_reset, corr_stage_read, corr_state, corr_status_str, corr_workspace_bytes)
 
 __all__ = [
     "Correlator", "CorrError", "corr_config", "corr_workspace_bytes", "corr_create", "corr_destroy",
@@ -21,7 +21,7 @@ __all__ = [
     "corr_dump_bytes", "corr_job_desc", "corr_sched_now", "corr_sched_create", "corr_sched_submit",
     "corr_sched_poll", "corr_sched_stats", "corr_sched_destroy", "Scheduler",
     "corr_status_str", "ENGINES", "SAMPLE_TYPES", "VOLT_FORMATS", "corr_aggregate_w16", "aggregate_w16",
-    "corr_cmac_design", "cmac_design", "DESIGNS",
+    "corr_cmac_design", "cmac_design", "DESIGNS", "corr_state", "corr_restore",
 ]
 
 ENGINES = {"fp32": CORR_X_FP32, "i8": CORR_X_I8, "f16": CORR_X_F16, "f8": CORR_X_F8, "fp32m": CORR_X_FP32M}
@@ -210,6 +210,17 @@ class Correlator:
 
     def seq_reset(self) -> None:
         corr_seq_reset(self.plan)
+
+    def state(self):
+        """(n_long, next_seq, seq_valid): what a checkpoint keeps besides the long-run sum."""
+        return corr_state(self.plan)
+
+    def restore(self, longrun, n_long: int, next_seq: int = 0, seq_valid: bool = False) -> None:
+        """Load a checkpoint: longrun is a float64 tensor [n_channels][P][2] (host or device)."""
+        t = self._torch
+        src = longrun.contiguous()
+        assert src.dtype == t.float64 and src.numel() == self.n_channels * self.n_products * 2
+        corr_restore(self.plan, src.data_ptr(), src.is_cuda, n_long, next_seq, seq_valid)
 
     def close(self) -> None:
         if getattr(self, "plan", 0):

@@ -40,6 +40,7 @@ EXPORTED = [
     "corr_correlate", "corr_dump", "corr_ring_read", "corr_stage_read", "corr_dump_bytes", "corr_status_str",
     "corr_sched_now", "corr_sched_create", "corr_sched_submit", "corr_sched_poll", "corr_sched_stats",
     "corr_sched_destroy", "corr_aggregate_w16", "corr_cmac_design", "corr_correlate_static",
+    "corr_state", "corr_restore",
 ]
 
 
@@ -100,6 +101,8 @@ def lib():
         L.corr_destroy.argtypes = [P]
         L.corr_channelise.argtypes = [P, P, I64, ctypes.c_uint64, P]
         L.corr_seq_reset.argtypes = [P]
+        L.corr_state.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(I32)]
+        L.corr_restore.argtypes = [P, P, I32, I64, ctypes.c_uint64, I32]
         L.corr_aggregate_w16.argtypes = [P, I32, I32, I64, ctypes.c_uint32, P, P, P]
         L.corr_cmac_design.argtypes = [I32, I32, P, I64, I32, I32, P, I32, P]
         L.corr_correlate.argtypes = [P, P, I64, I64]
@@ -174,6 +177,21 @@ def corr_channelise(plan: int, d_volt: int, n_blocks: int, first_seq: int, d_spe
 
 def corr_seq_reset(plan: int) -> None:
     _check(lib().corr_seq_reset(ctypes.c_void_p(plan)), "corr_seq_reset")
+
+
+def corr_state(plan: int):
+    """(n_long, next_seq, seq_valid) of a plan: what a checkpoint keeps besides the long-run sum."""
+    n = ctypes.c_int64(0)
+    seq = ctypes.c_uint64(0)
+    valid = ctypes.c_int32(0)
+    _check(lib().corr_state(ctypes.c_void_p(plan), ctypes.byref(n), ctypes.byref(seq), ctypes.byref(valid)),
+           "corr_state")
+    return int(n.value), int(seq.value), bool(valid.value)
+
+
+def corr_restore(plan: int, longrun: int, src_is_device: bool, n_long: int, next_seq: int, seq_valid: bool) -> None:
+    _check(lib().corr_restore(ctypes.c_void_p(plan), ctypes.c_void_p(longrun), int(src_is_device),
+                              ctypes.c_int64(n_long), ctypes.c_uint64(next_seq), int(seq_valid)), "corr_restore")
 
 
 def corr_correlate(plan: int, d_samples: int, n_samples: int, row_stride: int = 0) -> None:

@@ -427,6 +427,39 @@ corr_status corr_seq_reset(corr_plan* p) {
   return CORR_OK;
 }
 
+corr_status corr_state(const corr_plan* p, int64_t* n_long, uint64_t* next_seq, int32_t* seq_valid) {
+  if (!p) return CORR_E_INVAL;
+  if (n_long) *n_long = p->n_long;
+  if (next_seq) *next_seq = p->next_seq;
+  if (seq_valid) *seq_valid = p->seq_valid ? 1 : 0;
+  return CORR_OK;
+}
+
+corr_status corr_restore(corr_plan* p, const void* longrun, int32_t src_is_device, int64_t n_long,
+                         uint64_t next_seq, int32_t seq_valid) {
+  try {
+    if (!p) return CORR_E_INVAL;
+    if (p->error) return CORR_E_STATE;
+    if (!p->cfg.fp64_longrun || !longrun || n_long < 0) return CORR_E_INVAL;
+    hipError_t e = ensure_guards(p);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(at(p, p->L.longrun), longrun, p->L.longrun_bytes,
+                         src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(p, e);
+    p->n_long = n_long;
+    p->next_seq = next_seq;
+    p->seq_valid = seq_valid != 0;
+    p->acc_zero = true;
+    p->n_accum = 0;
+    p->ring_fill = 0;
+    p->stage_fill = 0;
+    return CORR_OK;
+  } catch (...) {
+    return CORR_E_INVAL;
+  }
+}
+
 corr_status corr_channelise(corr_plan* p, const void* d_volt, int64_t n_blocks, uint64_t first_seq,
                             float* d_spectra_dbg) {
   try {

@@ -135,6 +135,12 @@ static void plan_paths(int have_gpu)
             int64_t n = 0;
             int32_t exact = 0;
             (void)corr_dump(p, 16, ws, 1, &n, &exact);   /* an unknown flag bit */
+            int64_t n_long = -1;
+            uint64_t seq = 1;
+            int32_t valid = -1;
+            CHECK(corr_state(p, &n_long, &seq, &valid) == CORR_OK, "state");
+            CHECK(corr_state(p, NULL, NULL, NULL) == CORR_OK, "state, NULL outs");
+            CHECK(corr_restore(p, ws, 1, 10, 5, 1) != CORR_OK, "restore without a long-run sum");
             CHECK(corr_destroy(p) == CORR_OK, "destroy");
         }
     }

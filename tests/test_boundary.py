@@ -169,6 +169,10 @@ def test_host_checks_before_launch():
             _lib.corr_correlate(plan, fake + 1, 10, 0)       # misaligned int8 pairs
         assert e.value.status == _lib.CORR_E_INVAL
         assert _lib.corr_dump_bytes(plan, _lib.CORR_DUMP_INTEG) == 2 * 136 * 8
+        assert _lib.corr_state(plan) == (0, 0, False)                 # checkpoint state of a new plan
+        with pytest.raises(_lib.CorrError) as e:                       # no long-run sum to restore
+            _lib.corr_restore(plan, fake, True, 10, 5, True)
+        assert e.value.status == _lib.CORR_E_INVAL
     finally:
         _lib.corr_destroy(plan)
     cfg = _cfg(n_inputs=16, n_channels=2, engine="fp32", sample_type="ci8", max_abs=7)
