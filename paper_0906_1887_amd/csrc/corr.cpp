@@ -118,9 +118,9 @@ Layout layout_of(const corr_config* c) {
   const size_t pair_bytes = 8;  // int2 (int8 engine) or float2 (others)
   size_t off = 0;
   // each region is followed by a guard band (checked by corr_dump)
-  auto end_region = [&](size_t bytes) {
+  auto end_region = [&](size_t bytes) {   // at most 9 regions, below kMaxGuards
     off = align_up(off + bytes, kAlign);
-    L.guards.off[L.guards.n++] = off;
+    if (L.guards.n < corr::kMaxGuards) L.guards.off[L.guards.n++] = off;
     off += corr::kGuardBytes;
   };
   L.acc = off;
