@@ -581,11 +581,12 @@ def main() -> int:
     ap.add_argument("--serve-host-seconds", type=float, default=20.0)
     ap.add_argument("--serve-host-rate", type=float, default=100.0)
     ap.add_argument("--no-other-configs", action="store_true")
-    ap.add_argument("--mode", choices=["bench", "copy", "c2", "proto", "designs"], default="bench",
+    ap.add_argument("--mode", choices=["bench", "copy", "c2", "c4", "proto", "designs"], default="bench",
                     help="copy: only a 1 GiB device-to-device copy, the known-size reference for "
                          "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE counters; c2: only the C2 "
-                         "F-stage + X-engine timing (for profiling the F-stage); proto: only one second of "
-                         "the prototype's complex front end; designs: only the paper's CMAC designs")
+                         "F-stage + X-engine timing (for profiling the F-stage); c4: only the C4 FP16 / "
+                         "FP8 plans; proto: only one second of the prototype's complex front end; designs: "
+                         "only the paper's CMAC designs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -611,6 +612,9 @@ def main() -> int:
     stream = torch.cuda.current_stream(dev)
     if args.mode == "c2":
         print(json.dumps({"mode": "c2", **c2_config(dev, stream, reps=args.steps)}))
+        return 0
+    if args.mode == "c4":
+        print(json.dumps({"mode": "c4", **c4_config(dev, stream)}))
         return 0
     if args.mode == "proto":
         print(json.dumps({"mode": "proto", **prototype_config(dev, stream, reps=args.steps)}))
