@@ -239,16 +239,25 @@ def serving(seconds: float, warm: float, rate: float, host: bool, seed: int = 5)
 
 # HBM bytes per launch of the C3 int8 kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs calibrated against a 1 GiB device copy (FETCH x 2.000,
-# WRITE x 1.000); valid only for the kernel source they were taken on.
-TRAFFIC_SOURCE = os.path.join(ROOT, "paper_0906_1887_amd", "csrc", "xengine_mfma.hip")
-TRAFFIC_SHA1 = "e038011f8782945050b1fac0816841b0765e2170"
-TRAFFIC_BYTES = {"read": 2 * 16533686 * 1024, "write": 3274530 * 1024}
+# WRITE x 1.000); valid only for the sources they were taken on: the kernel,
+# its work-item order and the host code that sets up its launch.
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_0906_1887_amd", "csrc", f)
+                   for f in ("xengine_mfma.hip", "common.h", "corr.cpp")]
+TRAFFIC_SHA1 = "5a4cd264082f58b42929e4f9ec7440e2348b8991"
+TRAFFIC_BYTES = {"read": 2 * 27844318 * 1024, "write": 3384349 * 1024}
+
+
+def traffic_sources_sha1() -> str:
+    h = hashlib.sha1()
+    for path in TRAFFIC_SOURCES:
+        with open(path, "rb") as fh:
+            h.update(hashlib.sha1(fh.read()).digest())
+    return h.hexdigest()
 
 
 def measured_traffic():
-    with open(TRAFFIC_SOURCE, "rb") as fh:
-        if hashlib.sha1(fh.read()).hexdigest() != TRAFFIC_SHA1:
-            return None
+    if traffic_sources_sha1() != TRAFFIC_SHA1:
+        return None
     return TRAFFIC_BYTES["read"] + TRAFFIC_BYTES["write"]
 
 

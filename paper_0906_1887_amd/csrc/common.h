@@ -56,41 +56,18 @@ struct XArgs {
   int32_t n_items;          // n_ch * n_tiles * n_split
   int32_t per_xcd;          // ceil(n_items / 8)
   int32_t accumulate;       // 1: out += tile; 0: out = tile
-  int32_t order;            // 1: off-diagonal tiles first within each XCD (item_decode)
+  int32_t pad_;
   const float* inv_scale2;  // FP8: per-channel 1/s_c^2 applied in the epilogue (else null)
   const uint32_t* m_bits;   // converting FP8 engine: per-channel max |re|, |im| (float bits)
 };
 
-// Work item -> (channel, K split, tile I >= J) of the matrix-core engines.
-// order 0: tile fastest, then split, then channel.  order 1 (a pass without a
-// K split whose channels divide evenly over the XCDs, so that each XCD's
-// contiguous item range holds whole channels): each XCD first runs the
-// off-diagonal tiles of its channels, channel by channel, then their
-// diagonal tiles.  Workgroups resident together then run tiles of the same
-// length and stay close in K, so the row panels their tiles share are still
-// in the XCD's L2 when the second reader arrives; in the plain order the
-// shorter diagonal tiles (a quarter of their blocks is skipped) let the
-// starts drift apart.
+// Work item -> (channel, K split, tile I >= J) of the matrix-core engines:
+// tile fastest, then split, then channel, so that a channel's tiles (which
+// share its row panels) start together on one XCD (xcd_item keeps each XCD's
+// items contiguous).  An order that ran each XCD's off-diagonal tiles before
+// its diagonal ones read less from HBM on C3 but was measured slower there
+// (1.5 %) and on the FP16 engine (10 %), so it was removed.
 __device__ __forceinline__ void item_decode(const XArgs& a, int64_t item, int& ch, int& split, int& I, int& J) {
-  if (a.order == 1) {
-    int nb1, unused;
-    tile_decode(a.n_tiles - 1, nb1, unused);   // the last tile is (nb - 1, nb - 1)
-    const int nb = nb1 + 1;
-    const int n_off = a.n_tiles - nb;
-    const int64_t cpx = a.per_xcd / a.n_tiles;  // channels per XCD
-    const int64_t x = item / a.per_xcd, l = item % a.per_xcd;
-    split = 0;
-    if (l < cpx * n_off) {
-      ch = (int)(x * cpx + l / n_off);
-      tile_decode((int)(l % n_off), I, J);      // o = i(i+1)/2 + j, j <= i  ->  tile (i + 1, j)
-      I += 1;
-    } else {
-      const int64_t d = l - cpx * n_off;
-      ch = (int)(x * cpx + d / nb);
-      I = J = (int)(d % nb);
-    }
-    return;
-  }
   const int tile = (int)(item % a.n_tiles);
   const int64_t rest = item / a.n_tiles;
   split = (int)(rest % a.n_split);

@@ -281,14 +281,6 @@ corr_status corr_internal_xengine(const corr_xpass* q) {
   const bool aligned = (a.row_stride_b % 16 == 0) && ((reinterpret_cast<uintptr_t>(q->x) & 15) == 0);
   // nibble rows and FP32 matrix-core rows are staged 16 bytes at a time
   if ((q->elem == corr::kElemCI4 || q->elem == corr::kElemF32) && !aligned) return CORR_E_UNSUPPORTED;
-  // Off-diagonal tiles first within each XCD (see item_decode) when every XCD
-  // gets whole channels and there are off-diagonal tiles.  Not for the FP16 /
-  // FP8 engines: with few tiles per channel (3 at 256 inputs) that order runs
-  // a channel's off-diagonal tile long before its diagonal ones, each panel
-  // then comes from HBM twice (measured 2.0x the input), and the natural
-  // order, a channel's tiles started together, was 10 % faster.
-  const bool lowp = c.engine == CORR_X_F16 || c.engine == CORR_X_F8;
-  a.order = (split == 1 && c.n_channels % corr::kNumXcd == 0 && L.n_tiles > 1 && !lowp) ? 1 : 0;
 
   hipError_t e;
   const bool is_int = (c.engine == CORR_X_I8);

@@ -13,9 +13,9 @@ Cases:
 * every engine twice in fresh plans, with K split (64 inputs x 128 channels x
   1000 samples: 8 splits) and without (300 inputs x 16 channels x 2000);
 * the F-stage twice: the requantised ring and the FP32 spectra;
-* launch order: the int8 engine over 32 channels of 1024 inputs, where each
-  XCD's workgroups take its off-diagonal tiles first, against 31 channels of
-  the same samples in the natural tile order: equal on the 31.
+* launch mapping: the int8 engine over 32 channels of 1024 inputs against 31
+  channels of the same samples, whose work items land on other XCDs and
+  workgroup slots: equal on the 31.
 """
 import math
 import sys
@@ -79,10 +79,10 @@ def test_fstage_repeats_bit_for_bit():
     assert torch.equal(runs[0][1], runs[1][1])
 
 
-def test_tile_order_does_not_change_the_sums():
+def test_item_mapping_does_not_change_the_sums():
     n_in, T = 1024, 64
     x = torch.from_numpy(synth.ci8(seed=34, n_channels=32, n_inputs=n_in, n_samples=T)).to(DEV)
-    say("[determinism] 32 channels (off-diagonal tiles first) against 31 (natural order)")
+    say("[determinism] 32 channels against 31 (another item-to-XCD mapping)")
     a = dump_once("i8", "ci8", x, 7)
     b = dump_once("i8", "ci8", x[:31].contiguous(), 7)
     assert torch.equal(a[:31], b)
