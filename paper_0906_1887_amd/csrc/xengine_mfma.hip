@@ -623,8 +623,8 @@ __device__ __forceinline__ void mfma_tile_128(const XArgs& a, int8_t* lds, int c
 // for FP8).  The MFMA stage is that of mfma_tile_128, so the sums are those
 // of the staged engine on the same codes.  Two LDS stage buffers, one
 // barrier per stage, one workgroup per CU (the register prefetch takes the
-// room of a second).  Samples past the pass are zero; rows past N_I are read
-// from a clamped row and never stored.
+// room of a second; cvt_waves below sets its wave count).  Samples past the
+// pass are zero; rows past N_I are read from a clamped row and never stored.
 constexpr int kPF = 3;   // stages of float32 samples in flight per workgroup
 
 // Two floats -> two binary16 (round to nearest even), the first in the low half.
@@ -632,9 +632,17 @@ __device__ __forceinline__ uint32_t pack_f16x2(float lo, float hi) {
   return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)lo) | ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)hi) << 16);
 }
 
-template <int EK, bool DIAG>
+// NW waves per workgroup: 2 rows of NW / 2 waves, each wave a 64 x (256 / NW)
+// part of the tile (32 x 32 blocks 2 x NBN).  In a diagonal tile a block whose
+// columns lie above its rows is skipped, and a wave with no block left only
+// converts and keeps the barriers.
+template <int EK, bool DIAG, int NW>
 __device__ __forceinline__ void mfma_tile_128_cvt(const XArgs& a, int8_t* lds, int ch, int split, int I, int J) {
   constexpr int EKM = EK == kElemF16Cvt ? kElemF16 : kElemF8;   // the MFMA stage's element kind
+  static_assert(NW == 4 || NW == 8, "4 or 8 waves");
+  constexpr int NT = NW * 64;                     // threads
+  constexpr int NWN = NW / 2;                     // waves across the tile's columns
+  constexpr int NBN = 4 / NWN;                    // 32-column blocks per wave
   constexpr int BT = 128;
   constexpr int PANEL = BT * kMKC;                // bytes per operand per stage
   constexpr int STAGE = PANEL * (DIAG ? 1 : 2);
@@ -642,7 +650,7 @@ __device__ __forceinline__ void mfma_tile_128_cvt(const XArgs& a, int8_t* lds, i
   constexpr int SB = EKM == kElemF16 ? 4 : 2;     // staged bytes per complex sample
   constexpr int SPS = kMKC / SB;                  // samples per row per stage
   constexpr int NF = SPS / 2;                     // float4 (two samples) per row per stage
-  constexpr int L = BT * NF / 256;                // float4 per thread per operand per stage
+  constexpr int L = BT * NF / NT;                 // float4 per thread per operand per stage
   using Acc = typename MAcc<EKM>::T;
 
   const float* __restrict__ xc = reinterpret_cast<const float*>(static_cast<const int8_t*>(a.x) + (int64_t)ch * a.ch_stride_b);
@@ -659,7 +667,7 @@ __device__ __forceinline__ void mfma_tile_128_cvt(const XArgs& a, int8_t* lds, i
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / NWN, wn = wave % NWN;
 
   // This thread's loads: row q_row[q] (of 128), float4 f = q_f[q] of the
   // row's stage; LDS byte offset of the converted bytes within a panel.
@@ -667,7 +675,7 @@ __device__ __forceinline__ void mfma_tile_128_cvt(const XArgs& a, int8_t* lds, i
   int q_f[L], q_lds[L];
 #pragma unroll
   for (int q = 0; q < L; ++q) {
-    const int idx = tid + 256 * q;
+    const int idx = tid + NT * q;
     const int r = idx / NF, f = idx % NF;
     const int kb = f * 2 * SB;                   // K byte of the float4's first sample
     q_f[q] = f;
@@ -723,11 +731,11 @@ __device__ __forceinline__ void mfma_tile_128_cvt(const XArgs& a, int8_t* lds, i
       }
   };
 
-  Acc vr[2][2], vi[2][2];
+  Acc vr[2][NBN], vi[2][NBN];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int n = 0; n < 2; ++n)
+    for (int n = 0; n < NBN; ++n)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         vr[m][n][r] = 0;
@@ -736,7 +744,7 @@ __device__ __forceinline__ void mfma_tile_128_cvt(const XArgs& a, int8_t* lds, i
 
   const int frow = lane & 31;
   const int g = lane >> 5;
-  auto read = [&](int buf, v4i (&af)[2][2], v4i (&bf)[2][2]) {
+  auto read = [&](int buf, v4i (&af)[2][2], v4i (&bf)[NBN][2]) {
     const int8_t* As = lds + buf * STAGE;
     const int8_t* Bs = DIAG ? As : As + PANEL;
 #pragma unroll
@@ -748,22 +756,24 @@ __device__ __forceinline__ void mfma_tile_128_cvt(const XArgs& a, int8_t* lds, i
         af[m][h] = *reinterpret_cast<const v4i*>(As + r * kMKC + 16 * (cidx ^ swz(r)));
       }
 #pragma unroll
-      for (int n = 0; n < 2; ++n) {
-        const int r = wn * 64 + n * 32 + frow;
+      for (int n = 0; n < NBN; ++n) {
+        const int r = (wn * NBN + n) * 32 + frow;
         bf[n][h] = *reinterpret_cast<const v4i*>(Bs + r * kMKC + 16 * (cidx ^ swz(r)));
       }
     }
   };
-  const bool idle = DIAG && wm < wn;        // strictly upper quarter of a diagonal tile
-  const bool sk = DIAG && wm == wn;         // diagonal quarter: skip block (0, 1)
-  auto compute = [&](const v4i (&af)[2][2], const v4i (&bf)[2][2]) {
+  // 32 x 32 block (m, n) of this wave: rows 2 wm + m, columns wn NBN + n (in
+  // blocks); above the diagonal of a diagonal tile it is skipped.
+  auto skip = [&](int m, int n) { return DIAG && wn * NBN + n > 2 * wm + m; };
+  const bool idle = DIAG && wn * NBN > 2 * wm + 1;   // every block of the wave skipped
+  auto compute = [&](const v4i (&af)[2][2], const v4i (&bf)[NBN][2]) {
     v4i ra[2][2];
     if constexpr (EKM == kElemF8) {
 #pragma unroll
       for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int n = 0; n < 2; ++n)
-          if (!(sk && m == 0 && n == 1)) mfma64<EKM>(af[m], bf[n], vr[m][n]);
+        for (int n = 0; n < NBN; ++n)
+          if (!skip(m, n)) mfma64<EKM>(af[m], bf[n], vr[m][n]);
 #pragma unroll
       for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -771,16 +781,16 @@ __device__ __forceinline__ void mfma_tile_128_cvt(const XArgs& a, int8_t* lds, i
 #pragma unroll
       for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int n = 0; n < 2; ++n)
-          if (!(sk && m == 0 && n == 1)) mfma64<EKM>(ra[m], bf[n], vi[m][n]);
+        for (int n = 0; n < NBN; ++n)
+          if (!skip(m, n)) mfma64<EKM>(ra[m], bf[n], vi[m][n]);
     } else {
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int m = 0; m < 2; ++m)
 #pragma unroll
-          for (int n = 0; n < 2; ++n)
-            if (!(sk && m == 0 && n == 1)) mfma16<EKM>(af[m][h], bf[n][h], vr[m][n]);
+          for (int n = 0; n < NBN; ++n)
+            if (!skip(m, n)) mfma16<EKM>(af[m][h], bf[n][h], vr[m][n]);
 #pragma unroll
       for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -790,8 +800,8 @@ __device__ __forceinline__ void mfma_tile_128_cvt(const XArgs& a, int8_t* lds, i
 #pragma unroll
         for (int m = 0; m < 2; ++m)
 #pragma unroll
-          for (int n = 0; n < 2; ++n)
-            if (!(sk && m == 0 && n == 1)) mfma16<EKM>(ra[m][h], bf[n][h], vi[m][n]);
+          for (int n = 0; n < NBN; ++n)
+            if (!skip(m, n)) mfma16<EKM>(ra[m][h], bf[n][h], vi[m][n]);
     }
   };
 
@@ -811,7 +821,7 @@ __device__ __forceinline__ void mfma_tile_128_cvt(const XArgs& a, int8_t* lds, i
   auto step = [&](auto U, int st) {
     constexpr int u = decltype(U)::value;
     constexpr int nx = (u + 1) % kPF;
-    v4i af[2][2], bf[2][2];
+    v4i af[2][2], bf[NBN][2];
     if (!idle) read(st & 1, af, bf);
     if (st + 1 < n_st) {
       cvt_store(std::integral_constant<int, nx>{}, (st + 1) & 1);   // the buffer last read in stage st - 1
@@ -833,9 +843,9 @@ __device__ __forceinline__ void mfma_tile_128_cvt(const XArgs& a, int8_t* lds, i
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int n = 0; n < 2; ++n) {
-      if (sk && m == 0 && n == 1) continue;
-      const int j = J * BT + wn * 64 + n * 32 + (lane & 31);
+    for (int n = 0; n < NBN; ++n) {
+      if (skip(m, n)) continue;
+      const int j = J * BT + (wn * NBN + n) * 32 + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int i = I * BT + wm * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -1184,16 +1194,23 @@ __global__ __launch_bounds__(256, 2) void xeng_mfma_128_kernel(XArgs a) {
   }
 }
 
+// Waves per workgroup of the converting engines (one workgroup per CU).  FP16:
+// 8 (two per SIMD, 64 x 32 wave parts, 177 VGPRs), 8 % faster on C4 than 4
+// waves of 64 x 64.  FP8 stages twice the samples per row and would spill
+// with 8, so it keeps 4 (measured slower with 8).
 template <int EK>
-__global__ __launch_bounds__(256, 1) void xeng_cvt_128_kernel(XArgs a) {
+constexpr int cvt_waves() { return EK == kElemF16Cvt ? 8 : 4; }
+
+template <int EK>
+__global__ __launch_bounds__(cvt_waves<EK>() * 64, 1) void xeng_cvt_128_kernel(XArgs a) {
   __shared__ __attribute__((aligned(1024))) int8_t lds[2 * 2 * 128 * kMKC];
   const int64_t slot = blockIdx.x / kNumXcd;
   const int64_t item = xcd_item(blockIdx.x, a.per_xcd);
   if (slot >= a.per_xcd || item >= a.n_items) return;
   int ch, split, I, J;
   item_decode(a, item, ch, split, I, J);
-  if (I == J) mfma_tile_128_cvt<EK, true>(a, lds, ch, split, I, J);
-  else mfma_tile_128_cvt<EK, false>(a, lds, ch, split, I, J);
+  if (I == J) mfma_tile_128_cvt<EK, true, cvt_waves<EK>()>(a, lds, ch, split, I, J);
+  else mfma_tile_128_cvt<EK, false, cvt_waves<EK>()>(a, lds, ch, split, I, J);
 }
 
 // FP32 matrix-core tile: the 64-row tile of mfma_tile (same staging,
@@ -1525,10 +1542,10 @@ hipError_t launch_xeng_mfma(const XArgs& a, int elem, int bt, hipStream_t s) {
     CORR_LAUNCH(kElemF32, 64);   // 64-row tiles only
   } else if (elem == kElemCI4) {
     CORR_LAUNCH_W2(kElemCI4);   // 128-row tiles only
-  } else if (elem == kElemF16Cvt) {
-    hipLaunchKernelGGL((xeng_cvt_128_kernel<kElemF16Cvt>), g, b, 0, s, a);   // 128-row tiles only
+  } else if (elem == kElemF16Cvt) {   // 128-row tiles only
+    hipLaunchKernelGGL((xeng_cvt_128_kernel<kElemF16Cvt>), g, dim3(cvt_waves<kElemF16Cvt>() * 64), 0, s, a);
   } else if (elem == kElemF8Cvt) {
-    hipLaunchKernelGGL((xeng_cvt_128_kernel<kElemF8Cvt>), g, b, 0, s, a);
+    hipLaunchKernelGGL((xeng_cvt_128_kernel<kElemF8Cvt>), g, dim3(cvt_waves<kElemF8Cvt>() * 64), 0, s, a);
   } else if (elem == kElemF16) {
     if (bt == 128) CORR_LAUNCH_W2(kElemF16); else CORR_LAUNCH(kElemF16, 64);
   } else {
