@@ -243,8 +243,8 @@ def serving(seconds: float, warm: float, rate: float, host: bool, seed: int = 5)
 # its work-item order and the host code that sets up its launch.
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_0906_1887_amd", "csrc", f)
                    for f in ("xengine_mfma.hip", "common.h", "corr.cpp")]
-TRAFFIC_SHA1 = "5a4cd264082f58b42929e4f9ec7440e2348b8991"
-TRAFFIC_BYTES = {"read": 2 * 27844318 * 1024, "write": 3384349 * 1024}
+TRAFFIC_SHA1 = "4ac8600869ec0e3f23c25b49e51da4f5d1d31694"
+TRAFFIC_BYTES = {"read": 2 * 27747551 * 1024, "write": 3384225 * 1024}
 
 
 def traffic_sources_sha1() -> str:
