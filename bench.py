@@ -463,9 +463,10 @@ def c2_config(dev, stream, reps=20):
     # C2: F-stage (256-pt real FFT, requantise, corner turn) and X on the ring, N_I=64
     n_in, nb = 64, 10000
     s_req = float(torch.tensor(2.0 / (16.0 * 128 ** 0.5), dtype=torch.float32))
-    g = torch.Generator(device=dev).manual_seed(2)
-    volt = torch.clamp(torch.round(16.0 * torch.randn((nb * 256, n_in), device=dev, generator=g)), -128, 127)
-    volt = volt.to(torch.int8).contiguous()
+    # the C2 streams: Gaussian sigma 16, a common tone at channel 37, 10 % of
+    # the noise power common to inputs 0..7 (the tests' generator)
+    import synth
+    volt = torch.from_numpy(synth.real_voltages(seed=2, index=0, n_blocks=nb, n_inputs=n_in)).to(dev)
     c = Correlator(n_in, 128, engine="i8", fft_size=256, max_abs=7, requant_scale=s_req, ring_samples=nb,
                    device=str(dev))
     seq = [0]
@@ -532,6 +533,28 @@ def c2_config(dev, stream, reps=20):
     return out
 
 
+def c4_samples(dev, n_ch, n_in, T, seed=4, rho=0.1):
+    """The C4 inputs on the device: complex Gaussian samples of unit variance,
+    per-input gains in [0.5, 2] and coherence rho on 16 disjoint input pairs
+    (the recipe of synth.complex_float, with the same gains and pairs; the
+    noise comes from torch's device generator, 8.6 GB being too large to draw
+    on the host)."""
+    import math
+    import torch
+    import synth
+    gains = torch.tensor(synth.input_gains(seed, n_in), dtype=torch.float32, device=dev)
+    g = torch.Generator(device=dev).manual_seed(seed)
+    s = math.sqrt(0.5)
+    x = torch.randn((n_ch, n_in, T, 2), device=dev, generator=g)
+    x *= s
+    for a, b in synth.coherent_pairs(seed, n_in, 16):
+        c = torch.randn((n_ch, T, 2), device=dev, generator=g) * s
+        x[:, a] = math.sqrt(1.0 - rho) * x[:, a] + math.sqrt(rho) * c
+        x[:, b] = math.sqrt(1.0 - rho) * x[:, b] + math.sqrt(rho) * c
+    x *= gains.view(1, n_in, 1, 1)
+    return x
+
+
 def c4_config(dev, stream):
     import torch
     from paper_0906_1887_amd import Correlator, perfmodel
@@ -543,8 +566,7 @@ def c4_config(dev, stream):
     # X-engine's loads) and, beside it, the staged plan (a conversion pass
     # writes FP16 / FP8 rows that the X-engine then reads)
     n_in, n_ch, T = 256, 1024, 4096
-    g = torch.Generator(device=dev).manual_seed(4)
-    xf = torch.randn((n_ch, n_in, T, 2), device=dev, generator=g)
+    xf = c4_samples(dev, n_ch, n_in, T)
     cm = perfmodel.xengine_cmac(n_ch, n_in, T)
     out_bytes = n_ch * (n_in * (n_in + 1) // 2) * 8
     for engine, peak, sb in (("f16", perfmodel.MI355X["fp16_flops"], 4), ("f8", perfmodel.MI355X["fp8_flops"], 2)):
