@@ -142,7 +142,9 @@ def test_c4_full_size_errors():
     """N_I=256, 1024 channels, 4096 samples of complex Gaussian floats (gains
     in [0.5, 2], coherence 0.1 on 16 pairs): FP16 and FP8 engines against the
     FP64 oracle on 8 sampled channels, kernel-only (pinned) and total
-    (reported); the FP32 engine within 1e-5."""
+    (reported); the FP32 engine within 1e-5.  The converting plans (the
+    launch configuration the benchmark times) equal the staged plans on every
+    product."""
     n_in, n_ch, T, seed = 256, 1024, 4096, 4
     say("[C4] generating")
     x = np.empty((n_ch, n_in, T, 2), dtype=np.float32)
@@ -167,6 +169,14 @@ def test_c4_full_size_errors():
             say(f"    kernel-only rel. Frobenius error: max {kerr.max():.3e}")
             assert kerr.max() < KERNEL_TOL[engine]["c4"], (engine, kerr.max())
         c.close()
+        if engine != "fp32":
+            say(f"[C4] {engine} converting plan")
+            cv = Correlator(n_in, n_ch, engine=engine, sample_type="cf32", max_abs=0, ring_samples=0, device=DEV)
+            cv.correlate(xt, T)
+            out_cv, n_cv, _ = cv.dump(CORR_DUMP_INTEG, device_out=True)
+            cv.close()
+            assert n_cv == T and torch.equal(out_cv, out), engine
+            del out_cv
         tot = rel_fro(V, W64)
         norm = np.sqrt(W64[:, oracle.baseline_index(np.arange(n_in), np.arange(n_in)), 0])
         results[engine] = float(tot.max())

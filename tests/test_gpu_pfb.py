@@ -87,3 +87,26 @@ def test_pfb_unsupported_configs():
     with pytest.raises(CorrError):
         Correlator(8, 128, engine="i8", fft_size=128, max_abs=7, requant_scale=S, ring_samples=16, device=DEV,
                    volt_format="cw16", pfb_taps=4)
+
+
+def test_pfb_full_c2_size_sampled_blocks():
+    """The benchmark's filterbank launch: 64 inputs, 10 000 blocks (+3 of
+    history) in one call.  The ring and the FP32 spectra of 40 blocks (both
+    ends, workgroup boundaries, random others) meet the three checks against
+    the oracle's filterbank, each block from its own 4-block window."""
+    n_in, nb = 64, 10000
+    v = synth.real_voltages(seed=2, index=0, n_blocks=nb + P - 1, n_inputs=n_in)
+    say(f"[pfb] full size: {n_in} inputs, {nb} blocks")
+    c = plan(n_in, nb, P)
+    dbg = torch.empty((128, n_in, nb, 2), dtype=torch.float32, device=DEV)
+    c.channelise(torch.from_numpy(v).to(DEV), first_seq=0, spectra_dbg=dbg)
+    q = c.ring_read().numpy()
+    c.close()
+    rng = np.random.default_rng(12)
+    blocks = sorted(set([0, 1, 15, 16, 17, 63, 64, 4999, 5000, 9983, 9984, 9998, 9999]
+                        + rng.integers(0, nb, 27).tolist()))
+    X = np.concatenate([oracle.pfb_real(v[b * 256:(b + P) * 256], 256, P) for b in blocks], axis=2)
+    bound = max(fcheck.pfb_bound(v[b * 256:(b + P) * 256], 256, P) for b in blocks)
+    idx = torch.tensor(blocks, device=DEV)
+    Xg = dbg.index_select(2, idx).cpu().numpy()
+    fcheck.check_spectra_requant(X, Xg, q[:, :, blocks], S, 7, bound, "pfb full size")
