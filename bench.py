@@ -239,11 +239,12 @@ def serving(seconds: float, warm: float, rate: float, host: bool, seed: int = 5)
 
 # HBM bytes per launch of the C3 int8 kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs calibrated against a 1 GiB device copy (FETCH x 2.000,
-# WRITE x 1.000); valid only for the sources they were taken on: the kernel,
-# its work-item order and the host code that sets up its launch.
+# WRITE x 1.000); valid only for the sources they were taken on: the kernel
+# and its work-item order (the C3 pass has one launch shape: no K split,
+# 128-row tiles).
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_0906_1887_amd", "csrc", f)
-                   for f in ("xengine_mfma.hip", "common.h", "corr.cpp")]
-TRAFFIC_SHA1 = "4ac8600869ec0e3f23c25b49e51da4f5d1d31694"
+                   for f in ("xengine_mfma.hip", "common.h")]
+TRAFFIC_SHA1 = "741d6467e5b9e6b75761ef52d94a48101ab898a2"
 TRAFFIC_BYTES = {"read": 2 * 27747551 * 1024, "write": 3384225 * 1024}
 
 

@@ -125,6 +125,19 @@ hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Any address and length (a kernel, not a memset node, also under stream capture).
+__global__ void fill_zero_bytes_kernel(uint8_t* __restrict__ p, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0;
+}
+
+hipError_t launch_fill_zero_bytes(void* p, int64_t bytes, hipStream_t s) {
+  if (bytes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero_bytes_kernel, dim3(grid_for(bytes, 256)), dim3(256), 0, s, static_cast<uint8_t*>(p),
+                     bytes);
+  return hipGetLastError();
+}
+
 // Guard word w of band g: a position-dependent pattern, so that a band copied
 // or shifted onto another is also seen.
 __device__ __forceinline__ uint32_t guard_word(int g, int w) {

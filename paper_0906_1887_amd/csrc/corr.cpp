@@ -703,7 +703,7 @@ corr_status corr_dump(corr_plan* p, int32_t what, void* dst, int32_t dst_is_devi
         if (dst_is_device) {
           e = (L.acc_bytes % 16 == 0 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0)
                   ? corr::launch_fill_zero(dst, (int64_t)L.acc_bytes, p->stream)
-                  : hipMemsetAsync(dst, 0, L.acc_bytes, p->stream);
+                  : corr::launch_fill_zero_bytes(dst, (int64_t)L.acc_bytes, p->stream);
         }
       } else {
         e = hipMemcpyAsync(dst, at(p, L.acc), L.acc_bytes, kind, p->stream);

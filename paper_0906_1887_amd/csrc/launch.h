@@ -23,7 +23,8 @@ hipError_t launch_xeng_f32(const XArgs& a, int sample_bytes, int bt, bool aligne
 hipError_t launch_reduce_splits(const void* part, int64_t n_pairs, int n_split, void* acc, int accumulate,
                                 bool is_int, hipStream_t s);
 hipError_t launch_fold_f64(double* L, const void* V, int64_t n_scalars, bool is_int, hipStream_t s);
-hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
+hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);   // 16-byte aligned, bytes / 16 words
+hipError_t launch_fill_zero_bytes(void* p, int64_t bytes, hipStream_t s);
 
 // Guard bands of a plan's workspace: kGuardBytes after each region, filled
 // with a pattern that depends on the band and the word, and compared later.

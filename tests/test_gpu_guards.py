@@ -96,3 +96,21 @@ def test_bands_hold_through_every_engine_and_the_fstage():
         c.correlate(None)
         c.dump(CORR_DUMP_INTEG | 4, device_out=True)                 # fold into the long-run sum too
         c.close()
+
+
+def test_zero_dump_to_unaligned_device_memory():
+    """A dump of an empty integration into device memory writes zeros, and only
+    the dump's bytes, also at an address that is not 16-byte aligned and a
+    length that is not a multiple of 16 (1 input, 1 channel: 8 bytes)."""
+    for n_in, n_ch in ((1, 1), (5, 3)):
+        nbytes = n_ch * (n_in * (n_in + 1) // 2) * 8
+        c = Correlator(n_in, n_ch, engine="i8", max_abs=7, device=DEV)
+        buf = torch.full((nbytes + 64,), 0x5A, dtype=torch.uint8, device=DEV)
+        off = 4
+        n = _lib.corr_dump(c.plan, CORR_DUMP_INTEG, buf.data_ptr() + off, True)[0]
+        torch.cuda.synchronize()
+        c.close()
+        assert n == 0
+        got = buf.cpu()
+        assert int(got[off:off + nbytes].abs().sum()) == 0, (n_in, n_ch)
+        assert bool((got[:off] == 0x5A).all()) and bool((got[off + nbytes:] == 0x5A).all()), (n_in, n_ch)
