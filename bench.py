@@ -244,8 +244,8 @@ def serving(seconds: float, warm: float, rate: float, host: bool, seed: int = 5)
 # 128-row tiles).
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_0906_1887_amd", "csrc", f)
                    for f in ("xengine_mfma.hip", "common.h")]
-TRAFFIC_SHA1 = "741d6467e5b9e6b75761ef52d94a48101ab898a2"
-TRAFFIC_BYTES = {"read": 2 * 27747551 * 1024, "write": 3384225 * 1024}
+TRAFFIC_SHA1 = "79285caf821679d4f687728b71c16aa7f0534d82"
+TRAFFIC_BYTES = {"read": 2 * 27758019 * 1024, "write": 3383636 * 1024}
 
 
 def traffic_sources_sha1() -> str:

@@ -1146,10 +1146,8 @@ __device__ __forceinline__ void mfma_tile_128_i8(const XArgs& a, int8_t* lds, in
     else run(std::false_type{});
   }
 
-  // Epilogue.  32 x 32 accumulator layout: register r of lane l holds row
-  // 8*(r/4) + 4*(l/32) + r%4, column l%32.
-  // 16 x 16 accumulator layout: register r of lane l holds row 4*(l/16) + r,
-  // column l%16.
+  // Epilogue.  16 x 16 accumulator layout: register r of lane l holds row
+  // 4*(l/16) + r, column l%16.
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
