@@ -244,8 +244,8 @@ def serving(seconds: float, warm: float, rate: float, host: bool, seed: int = 5)
 # 128-row tiles).
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_0906_1887_amd", "csrc", f)
                    for f in ("xengine_mfma.hip", "common.h")]
-TRAFFIC_SHA1 = "79285caf821679d4f687728b71c16aa7f0534d82"
-TRAFFIC_BYTES = {"read": 2 * 27758019 * 1024, "write": 3383636 * 1024}
+TRAFFIC_SHA1 = "85b74776252e1fe064bc1be4b03c5cc10555dacf"
+TRAFFIC_BYTES = {"read": 2 * 27766799 * 1024, "write": 3383890 * 1024}
 
 
 def traffic_sources_sha1() -> str:
